@@ -1,0 +1,50 @@
+"""Planted mistakes in copies of the oracle must trip at least one pin.
+
+Each case rewrites one expression of ``oracle/dd_oracle.c`` in a temporary
+copy, compiles it on the CPU and runs the full pin set against it.  All
+mutants keep every memory access in bounds.
+"""
+import os
+
+import pytest
+
+import oracle
+from oracle.build import SRC, build_oracle
+from tests import pins
+
+MUTANTS = {
+    "floor_instead_of_rint": ("const double r = rint(samples);", "const double r = floor(samples);"),
+    "band_edge_reference": ("f_min + (double)(C - 1) * df;", "f_min + (double)C * df;"),
+    "dm_grid_off_by_one": ("dm_first + (double)i * dm_step;", "dm_first + (double)(i + 1) * dm_step;"),
+    "constant_4148": ("(4150.0 * dm) * k;", "(4148.808 * dm) * k;"),
+    "forward_drops_channel_0": ("            for (int32_t ch = 0; ch < C; ++ch) {\n                const double *row",
+                                "            for (int32_t ch = 1; ch < C; ++ch) {\n                const double *row"),
+    "forward_half_delay": ("x + (int64_t)ch * x_stride + delay[(int64_t)i * C + ch];",
+                           "x + (int64_t)ch * x_stride + delay[(int64_t)i * C + ch] / 2;"),
+    "forward_reversed_dm_rows": ("x + (int64_t)ch * x_stride + delay[(int64_t)i * C + ch];",
+                                 "x + (int64_t)ch * x_stride + delay[(int64_t)(D - 1 - i) * C + ch];"),
+    "forward_reversed_channels": ("x + (int64_t)ch * x_stride + delay[(int64_t)i * C + ch];",
+                                  "x + (int64_t)ch * x_stride + delay[(int64_t)i * C + (C - 1 - ch)];"),
+    "adjoint_half_delay": ("const int64_t tau = t + d;", "const int64_t tau = t + d / 2;"),
+    "adjoint_drops_dm_0": ("        for (int32_t i = 0; i < D; ++i) {\n            const int64_t d",
+                           "        for (int32_t i = 1; i < D; ++i) {\n            const int64_t d"),
+    "adjoint_shift_by_one": ("if (tau >= 0 && tau < T_in)\n                    row[tau] += g[t];",
+                             "if (tau >= 1 && tau < T_in)\n                    row[tau - 1] += g[t];"),
+}
+
+
+def test_unmutated_oracle_passes():
+    pins.run_all(oracle.default())
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(SRC).read()
+    assert src.count(old) == 1, "mutation site not found exactly once"
+    mutated = tmp_path / "mutant.c"
+    mutated.write_text(src.replace(old, new))
+    lib = build_oracle(src=str(mutated), out=str(tmp_path / "libmutant.so"))
+    mutant = oracle.COracle(lib)
+    with pytest.raises(AssertionError):
+        pins.run_all(mutant)
