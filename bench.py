@@ -1,0 +1,247 @@
+"""Benchmark: brute-force dedispersion throughput on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload apertif|lofar]
+                    [--no-extra] [--no-cpu-baseline]
+
+A step is one forward dedispersion of one beam (Sclocco et al., Algorithm 1)
+with the input already resident in HBM: one launch of the library's kernel.
+The headline workload is the Apertif-shaped beam (1,024 channels over
+1,420-1,720 MHz, 20,000 samples/s, 20,000 output samples, 2,048 trial DMs
+0-511.75 step 0.25, float32 N(0,1) noise + 4 pulses).  Throughput is GFLOP/s
+with one FLOP per (DM, sample, channel) addition, the paper's convention.
+
+Printed: ONE JSON line with the headline figure, the roofline of the kernel,
+the CPU oracle's throughput on a bounded sample, and (unless --no-extra)
+secondary same-GPU measurements: LOFAR-shaped beam, u8/f16 storage, the
+adjoint and fwd+bwd step, and the 64-beam batched launch.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+HBM_PEAK_GBPS = 8000.0
+# binary32 adds: 256 CUs x 128 lanes/clk x 2.4 GHz (the published 157.3
+# TFLOP/s vector FP32 figure counts a fused multiply-add as two FLOPs).
+ADD_PEAK_TFLOPS = 256 * 128 * 2.4e9 / 1e12
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def compulsory_bytes(setup, in_bytes_per_sample, plan):
+    """Each input sample read once, each output written once (Eq. (3)'s
+    reuse limit), plus the delay table."""
+    return (setup.n_channels * plan.input_samples * in_bytes_per_sample
+            + setup.n_dm * setup.n_samples * 4 + setup.n_dm * setup.n_channels * 4)
+
+
+def timed(torch, fn, steps, warmup, stream):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def gpu_input(torch, setup, T, dtype, seed):
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    z = torch.randn((setup.n_channels, T), generator=g, device="cuda", dtype=torch.float32)
+    if dtype == "f32":
+        return z
+    if dtype == "f16":
+        return z.half()
+    return torch.clamp(torch.round(z * 16 + 128), 0, 255).to(torch.uint8)
+
+
+def measure_forward(torch, dd, setup, dtype, steps, warmup, stream, numpy_input=None):
+    plan = dd.Plan.from_setup(setup)
+    T = plan.input_samples
+    if numpy_input is not None:
+        x = torch.from_numpy(numpy_input).to("cuda")
+    else:
+        x = gpu_input(torch, setup, T, dtype, setup.seed)
+    out = torch.empty((setup.n_dm, setup.n_samples), dtype=torch.float32, device="cuda")
+    code = {"f32": dd.DD_F32, "f16": dd.DD_F16, "u8": dd.DD_U8}[dtype]
+    plan.prepare(dd.DD_FORWARD, code)
+    ms, wall = timed(torch, lambda: dd.dedisperse(x, plan, out=out), steps, warmup, stream)
+    bpe = {"f32": 4, "f16": 2, "u8": 1}[dtype]
+    return dict(ms=ms, wall_s=wall, gflops=setup.adds / (ms * 1e-3) / 1e9,
+                compulsory_bytes=compulsory_bytes(setup, bpe, plan), tile=plan.get_tile(dtype=code)), plan
+
+
+def cpu_baseline(setup, budget_s=12.0):
+    """The FP64 oracle on a bounded sample of the workload: the full input,
+    the first n trial DMs, n chosen so the timed run takes ~budget_s."""
+    import oracle
+    table = oracle.delay_table(*setup.plan_args()[:7])
+    T = setup.n_samples + int(table.max())
+    arrivals = {i: table[i] for i, _ in synth.pulse_sites(setup)}
+    x = synth.make_input(setup, T, "f32", arrivals=arrivals).astype(np.float64)
+    n = 4
+    t0 = time.perf_counter()
+    oracle.dedisperse(x, table[:n], setup.n_samples)
+    probe = time.perf_counter() - t0
+    n_dm = int(min(setup.n_dm, max(n, budget_s / max(probe, 1e-6) * n)))
+    t0 = time.perf_counter()
+    oracle.dedisperse(x, table[:n_dm], setup.n_samples)
+    dt = time.perf_counter() - t0
+    adds = n_dm * setup.n_samples * setup.n_channels
+    return {"value": adds / dt / 1e9, "unit": "GFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "%s input, first %d of %d trial DMs, all %d channels x %d samples (%.2e adds in %.1f s)"
+                      % (setup.name, n_dm, setup.n_dm, setup.n_channels, setup.n_samples, adds, dt)}
+
+
+def extras(torch, dd, stream, steps):
+    res = {}
+    # LOFAR-shaped beam, float32
+    r, _ = measure_forward(torch, dd, synth.LOFAR, "f32", steps, 2, stream)
+    r["hbm_GBps"] = r["compulsory_bytes"] / (r["ms"] * 1e-3) / 1e9
+    res["lofar_f32"] = r
+    log("lofar f32: %.3f ms %.1f GFLOP/s" % (r["ms"], r["gflops"]))
+    # low precision storage, Apertif
+    for dt in ("u8", "f16"):
+        r, _ = measure_forward(torch, dd, synth.APERTIF, dt, steps, 2, stream)
+        res["apertif_" + dt] = r
+        log("apertif %s: %.3f ms %.1f GFLOP/s" % (dt, r["ms"], r["gflops"]))
+    # adjoint and fwd+bwd (8 Apertif-shaped beams through autograd)
+    beams = synth.fwd_bwd_beams()
+    plans = [dd.Plan.from_setup(b) for b in beams]
+    xs = [gpu_input(torch, b, p.input_samples, "f32", b.seed).requires_grad_(True) for b, p in zip(beams, plans)]
+    ws = [torch.rand((b.n_dm, b.n_samples), device="cuda", generator=torch.Generator(device="cuda").manual_seed(b.seed + 1))
+          for b in beams]
+    for p in plans:
+        p.prepare(dd.DD_FORWARD, dd.DD_F32)
+        p.prepare(dd.DD_ADJOINT, dd.DD_F32)
+    gy = torch.randn((beams[0].n_dm, beams[0].n_samples), device="cuda")
+    ms_adj, _ = timed(torch, lambda: dd.dedisperse_adjoint(gy, plans[0]), steps, 2, stream)
+    res["apertif_adjoint"] = dict(ms=ms_adj, gflops=beams[0].adds / (ms_adj * 1e-3) / 1e9,
+                                  tile=plans[0].get_tile(direction=dd.DD_ADJOINT))
+    log("apertif adjoint: %.3f ms" % ms_adj)
+
+    def fwd_bwd():
+        for x, p, w in zip(xs, plans, ws):
+            x.grad = None
+            y = dd.Dedisperse.apply(x, p)
+            (w * y * y).sum().backward()
+
+    ms_fb, _ = timed(torch, fwd_bwd, max(2, steps // 4), 1, stream)
+    adds_fb = 2 * sum(b.adds for b in beams)
+    res["fwd_bwd_8beams"] = dict(ms=ms_fb, gflops=adds_fb / (ms_fb * 1e-3) / 1e9,
+                                 note="forward + adjoint adds of 8 beams per step, autograd incl. loss ops")
+    log("fwd+bwd 8 beams: %.3f ms" % ms_fb)
+    del xs, ws, gy
+    # batched: 64 uneven beams, one persistent launch
+    for dt, code in (("u8", dd.DD_U8), ("f16", dd.DD_F16)):
+        beams = synth.batched_beams()
+        plans = [dd.Plan.from_setup(b) for b in beams]
+        xs = [gpu_input(torch, b, p.input_samples, dt, b.seed) for b, p in zip(beams, plans)]
+        outs = [torch.empty((b.n_dm, b.n_samples), device="cuda") for b in beams]
+        batch = dd.Batch(plans, dtype=code)
+        ms_b, _ = timed(torch, lambda: batch.run(xs, outs), max(2, steps // 4), 1, stream)
+        # same beams one plain launch each (same storage type)
+        def singles():
+            for x, p, o in zip(xs, plans, outs):
+                dd.dedisperse(x, p, out=o)
+        ms_s, _ = timed(torch, singles, max(2, steps // 4), 1, stream)
+        res["batched64_" + dt] = dict(ms=ms_b, gflops=batch.adds / (ms_b * 1e-3) / 1e9,
+                                      per_beam_launches_ms=ms_s, adds=batch.adds)
+        log("batched %s: %.3f ms (%.1f GFLOP/s), per-beam launches %.3f ms" % (dt, ms_b, batch.adds / (ms_b * 1e-3) / 1e9, ms_s))
+        del xs, outs, batch
+        torch.cuda.empty_cache()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="apertif", choices=["apertif", "lofar"])
+    ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: dedispersion beams are independent and this build runs on a "
+              "single MI355X; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1601_05052_amd as dd
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    setup = synth.WORKLOADS[args.workload]
+
+    # Headline input: the seeded workload with its pulses (arrivals from the
+    # library's own plan; the timing does not depend on the values).
+    plan0 = dd.Plan.from_setup(setup)
+    table = plan0.delays()
+    arrivals = {i: table[i] for i, _ in synth.pulse_sites(setup)}
+    x = synth.make_input(setup, plan0.input_samples, "f32", arrivals=arrivals)
+    log("workload %s: C=%d D=%d S=%d T_in=%d" % (setup.name, setup.n_channels, setup.n_dm, setup.n_samples,
+                                                  plan0.input_samples))
+    r, plan = measure_forward(torch, dd, setup, "f32", args.steps, args.warmup, stream, numpy_input=x)
+    ms = r["ms"]
+    log("forward f32: %.4f ms/step, %.1f GFLOP/s, tile %d" % (ms, r["gflops"], r["tile"]))
+    achieved_tflops = setup.adds / (ms * 1e-3) / 1e12
+    hbm_gbps = r["compulsory_bytes"] / (ms * 1e-3) / 1e9
+    line = {
+        "metric": "dedispersion GFLOP/s (one FLOP per channel addition), Apertif-shaped beam, FP32",
+        "value": round(r["gflops"], 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "%s: %d channels %.0f-%.0f MHz, %d samples/s, %d output samples, %d trial DMs "
+                               "%.2f-%.2f step %.2f, float32 N(0,1) + pulses" % (
+                                   setup.name, setup.n_channels, setup.f_min,
+                                   setup.f_min + setup.n_channels * setup.df, round(1 / setup.t_samp),
+                                   setup.n_samples, setup.n_dm, setup.dm_first,
+                                   setup.dm_first + (setup.n_dm - 1) * setup.dm_step, setup.dm_step),
+                   "tile_variant": r["tile"]},
+        "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": round(ADD_PEAK_TFLOPS, 1),
+                     "unit": "TFLOP/s", "frac": round(achieved_tflops / ADD_PEAK_TFLOPS, 4), "traffic": None},
+        "hbm": {"compulsory_bytes": r["compulsory_bytes"], "achieved_GBps": round(hbm_gbps, 1),
+                "peak_GBps": HBM_PEAK_GBPS, "frac": round(hbm_gbps / HBM_PEAK_GBPS, 4)},
+        "paper_context": {"hd7970_2000dms_s": 0.106, "hd7970_GFLOPs": round(2000 * 1024 * 20000 / 0.106 / 1e9, 1),
+                          "note": "AMD HD7970, OpenCL, 2,000 DMs x 1 s Apertif (Sec. V-D); other hardware"},
+    }
+    if not args.no_extra:
+        line["extras"] = extras(torch, dd, stream, max(5, args.steps // 5))
+    if not args.no_cpu_baseline:
+        log("cpu baseline (FP64 oracle) ...")
+        line["cpu_baseline"] = cpu_baseline(setup)
+        log("cpu baseline: %.2f GFLOP/s on %d threads" % (line["cpu_baseline"]["value"], line["cpu_baseline"]["cores"]))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,212 @@
+/*
+ * dedisp.h -- C ABI of libdedisp, brute-force incoherent dedispersion on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The method is the one of Sclocco et al., "Auto-Tuning Dedispersion for
+ * Many-Core Accelerators" (arXiv:1601.05052):
+ *
+ *   delay[i][ch] = rint( 4150 * DM_i * (1/f_ch^2 - 1/f_h^2) / t_samp )
+ *                                  (Sec. II, Eq. (1), f in MHz, result in samples)
+ *   out[i][t]    = sum_ch in[ch][t + delay[i][ch]]        (Sec. III-A, Algorithm 1)
+ *
+ * for trial DMs DM_i = dm_first + i*dm_step (i < n_dm; Sec. IV sets the grid by
+ * its first value and step), channels f_ch = f_min + ch*df (ch < n_channels,
+ * channel 0 the lowest frequency) and f_h the top channel's frequency, so the
+ * top channel's delay is 0.  The delay table is evaluated on the host in IEEE
+ * binary64 (one rounding per operation, no contraction) and rounded half to
+ * even.  Sums run in binary32 on the GPU; the order over channels is not
+ * specified.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns DD_OK (0) or a negative dd_status.  On failure
+ *     dd_last_error() describes the cause (thread-local; valid until the
+ *     calling thread's next dd_* call).
+ *   - Argument, shape, stride and alignment errors are detected before any
+ *     GPU work is enqueued; nothing is written in that case.
+ *   - Device pointers are HIP device allocations on the current device.  The
+ *     caller owns every buffer; the library never frees or synchronises
+ *     caller memory or streams.  Work is enqueued asynchronously on `stream`
+ *     (a hipStream_t; NULL means the default stream).  Faults inside a kernel
+ *     surface at the caller's next synchronisation.
+ *   - Arrays are row-major; strides are in elements, not bytes.
+ *   - A plan is immutable after creation except for its tile choices and its
+ *     lazily built device tables (both guarded by a mutex), so one plan may be
+ *     used from several host threads and streams at once.
+ *   - The first call that uses a plan on a device uploads its tables with a
+ *     synchronous copy; make that first call outside HIP graph capture (or
+ *     call dd_plan_prepare first).
+ */
+#ifndef DEDISP_H
+#define DEDISP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dd_plan dd_plan;
+typedef struct dd_batch dd_batch;
+
+/* Input sample storage.  Accumulation is binary32 for every type.
+ * DD_F32: IEEE binary32.  DD_F16: IEEE binary16, widened exactly.
+ * DD_U8: unsigned 8-bit integers summed as their values (no zero point). */
+typedef enum dd_dtype { DD_F32 = 0, DD_F16 = 1, DD_U8 = 2 } dd_dtype;
+
+/* Which linear map a tile choice or a tuning run refers to. */
+typedef enum dd_direction { DD_FORWARD = 0, DD_ADJOINT = 1 } dd_direction;
+
+typedef enum dd_status {
+    DD_OK = 0,
+    DD_EINVAL = -1,       /* bad scalar argument or NULL pointer */
+    DD_ESHAPE = -2,       /* stride / size / alignment inconsistent with the plan */
+    DD_ENOMEM = -3,       /* host or device allocation failed */
+    DD_EHIP = -4,         /* a HIP runtime call or kernel launch failed */
+    DD_EUNSUPPORTED = -5  /* valid request this build cannot serve */
+} dd_status;
+
+/* ---------------------------------------------------------------- plans */
+
+/* Create a plan: validates the setup and computes the delay table on the
+ * host (Sec. II, Eq. (1); Sec. III-A notes it is computed in advance).
+ *   n_channels  >= 1          channels; channel ch at f_min_mhz + ch*df_mhz
+ *   f_min_mhz   > 0, finite   frequency of channel 0 (the lowest), MHz
+ *   df_mhz      > 0, finite   channel spacing, MHz
+ *   t_samp_s    > 0, finite   sampling time, seconds
+ *   dm_first    >= 0, finite  first trial DM, pc/cm^3
+ *   dm_step     >= 0, finite  DM increment, pc/cm^3
+ *   n_dm        >= 1          number of trial DMs
+ *   n_samples   >= 1          output samples per DM
+ * Fails with DD_EINVAL if a delay does not fit int32 or if n_samples plus
+ * the largest delay is 2^29 or more.  Touches no GPU.  *out receives the plan
+ * (caller destroys it with dd_plan_destroy). */
+int dd_plan_create(dd_plan **out, int32_t n_channels, double f_min_mhz, double df_mhz,
+                   double t_samp_s, double dm_first, double dm_step, int32_t n_dm,
+                   int64_t n_samples);
+
+/* Release a plan and its device tables on every device it used.  NULL is a
+ * no-op.  No call may be using the plan concurrently. */
+int dd_plan_destroy(dd_plan *plan);
+
+/* Plan dimensions (any output pointer may be NULL). */
+int dd_plan_dims(const dd_plan *plan, int32_t *n_channels, int32_t *n_dm, int64_t *n_samples);
+
+/* Largest delay in samples (delay[n_dm-1][0] for the monotone law). */
+int dd_plan_max_delay(const dd_plan *plan, int32_t *out);
+
+/* Input samples each channel row must hold: n_samples + max delay. */
+int dd_plan_input_samples(const dd_plan *plan, int64_t *out);
+
+/* Copy the delay table, n_dm*n_channels int32, row-major [dm][ch], into host
+ * memory owned by the caller. */
+int dd_plan_delay_table(const dd_plan *plan, int32_t *host_dst);
+
+/* Build and upload the device tables that `direction` with `in_type` needs on
+ * the current device, with a synchronous copy.  Optional: the compute calls
+ * do it on first use. */
+int dd_plan_prepare(dd_plan *plan, dd_direction direction, dd_dtype in_type);
+
+/* ---------------------------------------------------------------- compute */
+
+/* Forward dedispersion, Sec. III-A, Algorithm 1:
+ *   d_out[i*out_stride + t] = sum_ch d_in[ch*in_stride + t + delay[i][ch]]
+ * for i < n_dm, t < n_samples.
+ *   d_in       device, n_channels rows of in_stride elements of in_type;
+ *              in_stride >= n_samples + max_delay; aligned to the element size
+ *   d_out      device float, n_dm rows of out_stride >= n_samples; columns
+ *              [0, n_samples) are overwritten, padding is never touched
+ *   stream     hipStream_t or NULL
+ * d_in and d_out must not overlap. */
+int dd_dedisperse(const dd_plan *plan, const void *d_in, dd_dtype in_type, int64_t in_stride,
+                  float *d_out, int64_t out_stride, void *stream);
+
+/* Adjoint (transpose) of dd_dedisperse for binary32 data:
+ *   d_grad_in[ch*in_stride + tau] = sum over i with 0 <= tau - delay[i][ch] < n_samples
+ *                                   of d_grad_out[i*out_stride + tau - delay[i][ch]]
+ * for ch < n_channels and tau < n_samples + max_delay.  Written as a gather
+ * per channel over DMs (no atomics), so results are deterministic.
+ *   d_grad_out  device float, n_dm rows of out_stride >= n_samples
+ *   d_grad_in   device float, n_channels rows of in_stride >= n_samples + max_delay;
+ *               columns [0, n_samples + max_delay) are overwritten (zeros where
+ *               no output reads a sample), padding is never touched
+ * The two buffers must not overlap. */
+int dd_dedisperse_adjoint(const dd_plan *plan, const float *d_grad_out, int64_t out_stride,
+                          float *d_grad_in, int64_t in_stride, void *stream);
+
+/* ---------------------------------------------------------------- tiles */
+
+/* Number of compiled tile variants, and the shape of one: each work-group
+ * is `waves` wavefronts of 64 lanes; a lane owns `items_t` output samples of
+ * `items_acc` output rows (DMs forward, channels adjoint), so a work-group
+ * covers (64*items_t) samples x (waves*items_acc) rows -- the four parameters
+ * of the paper's Sec. III-B (work-items and elements per work-item, in time
+ * and in DM). */
+int dd_tile_count(int32_t *n_variants);
+int dd_tile_info(int32_t variant, int32_t *items_t, int32_t *items_acc, int32_t *waves,
+                 int32_t *kind);
+
+/* Force a tile variant for (direction, in_type) on this plan, or -1 to
+ * return to the automatic choice.  DD_EUNSUPPORTED if the variant cannot
+ * serve this plan (its staging window would not fit in LDS). */
+int dd_plan_set_tile(dd_plan *plan, dd_direction direction, dd_dtype in_type, int32_t variant);
+
+/* Tile variant the next call would use. */
+int dd_plan_get_tile(const dd_plan *plan, dd_direction direction, dd_dtype in_type,
+                     int32_t *variant);
+
+/* Auto-tuning, Sec. IV-A: time every tile variant that can serve this plan
+ * on the current device (mean of `reps` runs after one warm-up, on private
+ * scratch buffers allocated and freed here), keep the fastest for
+ * (direction, in_type) and report it.  If cache_path is non-NULL, the result
+ * is looked up in / appended to that text file, keyed by device architecture,
+ * direction, dtype and plan shape.  Synchronises `stream`.
+ *   best_variant  out, may be NULL
+ *   best_ms       out, mean milliseconds of the best variant, may be NULL */
+int dd_autotune(dd_plan *plan, dd_direction direction, dd_dtype in_type, int32_t reps,
+                const char *cache_path, void *stream, int32_t *best_variant, float *best_ms);
+
+/* ---------------------------------------------------------------- batches */
+
+/* Many independent beams (Sec. III-A treats one beam without loss of
+ * generality; beams are independent) dedispersed by ONE persistent kernel
+ * launch.  The batch keeps pointers to the plans, which must outlive it;
+ * every beam uses in_type.  Work items are ordered by cost (largest first)
+ * and handed out through a device counter. */
+int dd_batch_create(dd_batch **out, const dd_plan *const *plans, int32_t n_beams,
+                    dd_dtype in_type);
+
+/* Auto-tune each plan's forward tile for the batch kernel (Sec. IV-A), over
+ * the variants the batch kernel compiles, timing single-beam launches of each
+ * plan on private scratch buffers (allocated and freed here).  The choice is
+ * stored in the plan and used by the next dd_batch_create; cache_path as in
+ * dd_autotune.  Synchronises `stream`. */
+int dd_batch_autotune(dd_plan *const *plans, int32_t n_beams, dd_dtype in_type, int32_t reps,
+                      const char *cache_path, void *stream);
+
+/* Run every beam: for beam b, the forward of plans[b] on d_in[b] (row stride
+ * in_strides[b] elements) into d_out[b] (row stride out_strides[b]).  The
+ * pointer arrays are host arrays of n_beams device pointers; they are copied
+ * into a device descriptor table on `stream` before the launch, so the host
+ * arrays may be reused when the call returns.  Same per-beam requirements
+ * as dd_dedisperse. */
+int dd_batch_run(dd_batch *batch, const void *const *d_in, const int64_t *in_strides,
+                 float *const *d_out, const int64_t *out_strides, void *stream);
+
+/* Total additions (sum over beams of n_dm*n_samples*n_channels). */
+int dd_batch_adds(const dd_batch *batch, double *adds);
+
+int dd_batch_destroy(dd_batch *batch);
+
+/* ---------------------------------------------------------------- errors */
+
+/* Message for the calling thread's last failure ("" if none). */
+const char *dd_last_error(void);
+
+/* Library version string. */
+const char *dd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEDISP_H */

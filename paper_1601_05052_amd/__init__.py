@@ -1,0 +1,266 @@
+"""Brute-force incoherent dedispersion on AMD MI355X (gfx950).
+
+Python view of libdedisp (``include/dedisp.h``).  Every step of the
+computation runs in the library's HIP kernels; this module only passes
+pointers, sizes and the current HIP stream.  PyTorch supplies device memory
+and streams.  If the library is not built, importing the bindings raises --
+there is no CPU fallback.
+
+    plan = Plan(n_channels, f_min, df, t_samp, dm_first, dm_step, n_dm, n_samples)
+    y = dedisperse(x, plan)                 # x: [C][>= plan.input_samples] f32/f16/u8 on GPU
+    y = Dedisperse.apply(x, plan)           # differentiable (adjoint in backward)
+    Batch([plan_a, plan_b, ...]).run([xa, xb, ...])
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import DD_ADJOINT, DD_F16, DD_F32, DD_FORWARD, DD_U8, DedispError, check  # noqa: F401
+
+__all__ = ["Plan", "Batch", "Dedisperse", "dedisperse", "dedisperse_adjoint", "DedispError",
+           "tile_variants", "DD_F32", "DD_F16", "DD_U8", "DD_FORWARD", "DD_ADJOINT"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t == torch.float32:
+        return DD_F32
+    if t == torch.float16:
+        return DD_F16
+    if t == torch.uint8:
+        return DD_U8
+    raise TypeError("input dtype must be float32, float16 or uint8 (got %s)" % t)
+
+
+def _stream_handle(device) -> ctypes.c_void_p:
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def tile_variants():
+    """[(id, items_t, items_acc, waves, kind)] of the compiled tile variants."""
+    n = ctypes.c_int32()
+    check(_lib.lib().dd_tile_count(ctypes.byref(n)))
+    out = []
+    for v in range(n.value):
+        a, b, c, k = (ctypes.c_int32() for _ in range(4))
+        check(_lib.lib().dd_tile_info(v, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(k)))
+        out.append((v, a.value, b.value, c.value, k.value))
+    return out
+
+
+class Plan:
+    """A dedispersion plan: setup + DM grid + the FP64 delay table."""
+
+    def __init__(self, n_channels: int, f_min: float, df: float, t_samp: float, dm_first: float,
+                 dm_step: float, n_dm: int, n_samples: int):
+        L = _lib.lib()
+        h = ctypes.c_void_p()
+        check(L.dd_plan_create(ctypes.byref(h), int(n_channels), float(f_min), float(df), float(t_samp),
+                               float(dm_first), float(dm_step), int(n_dm), int(n_samples)))
+        self._h = h
+        self.n_channels = int(n_channels)
+        self.n_dm = int(n_dm)
+        self.n_samples = int(n_samples)
+        md = ctypes.c_int32()
+        check(L.dd_plan_max_delay(h, ctypes.byref(md)))
+        self.max_delay = md.value
+        ti = ctypes.c_int64()
+        check(L.dd_plan_input_samples(h, ctypes.byref(ti)))
+        self.input_samples = ti.value
+
+    @classmethod
+    def from_setup(cls, setup) -> "Plan":
+        return cls(*setup.plan_args())
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def delays(self) -> np.ndarray:
+        out = np.empty((self.n_dm, self.n_channels), dtype=np.int32)
+        check(_lib.lib().dd_plan_delay_table(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    @property
+    def adds(self) -> int:
+        return self.n_dm * self.n_samples * self.n_channels
+
+    def prepare(self, direction: int = DD_FORWARD, dtype: int = DD_F32) -> None:
+        check(_lib.lib().dd_plan_prepare(self._h, direction, dtype))
+
+    def set_tile(self, variant: int, direction: int = DD_FORWARD, dtype: int = DD_F32) -> None:
+        check(_lib.lib().dd_plan_set_tile(self._h, direction, dtype, int(variant)))
+
+    def get_tile(self, direction: int = DD_FORWARD, dtype: int = DD_F32) -> int:
+        v = ctypes.c_int32()
+        check(_lib.lib().dd_plan_get_tile(self._h, direction, dtype, ctypes.byref(v)))
+        return v.value
+
+    def autotune(self, direction: int = DD_FORWARD, dtype: int = DD_F32, reps: int = 3,
+                 cache_path: Optional[str] = None, device=None):
+        v, ms = ctypes.c_int32(), ctypes.c_float()
+        cp = cache_path.encode() if cache_path else None
+        check(_lib.lib().dd_autotune(self._h, direction, dtype, int(reps), cp, _stream_handle(device),
+                                     ctypes.byref(v), ctypes.byref(ms)))
+        return v.value, ms.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.lib().dd_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _check_input(x, plan: Plan):
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError("input must be a GPU tensor")
+    if x.dim() != 2 or x.shape[0] != plan.n_channels:
+        raise ValueError("input must be [n_channels][>= input_samples]")
+    if x.stride(1) != 1:
+        raise ValueError("input rows must be contiguous")
+    if x.shape[1] < plan.input_samples:
+        raise ValueError("input rows hold %d samples, the plan needs %d" % (x.shape[1], plan.input_samples))
+
+
+def dedisperse(x, plan: Plan, out=None):
+    """Forward dedispersion (Algorithm 1) of x [C][>= T_in] into out [D][S] float32."""
+    torch = _torch()
+    _check_input(x, plan)
+    if out is None:
+        out = torch.empty((plan.n_dm, plan.n_samples), dtype=torch.float32, device=x.device)
+    elif (out.dtype != torch.float32 or out.device != x.device or out.dim() != 2
+          or out.shape[0] != plan.n_dm or out.shape[1] < plan.n_samples or out.stride(1) != 1):
+        raise ValueError("out must be float32 [n_dm][>= n_samples] on the input's device")
+    with torch.cuda.device(x.device):
+        check(_lib.lib().dd_dedisperse(plan.handle, ctypes.c_void_p(x.data_ptr()), _dtype_code(x.dtype),
+                                       x.stride(0), ctypes.c_void_p(out.data_ptr()), out.stride(0),
+                                       _stream_handle(x.device)))
+    return out
+
+
+def dedisperse_adjoint(gy, plan: Plan, out=None):
+    """Adjoint of ``dedisperse``: gy [D][>= S] float32 -> [C][T_in] float32."""
+    torch = _torch()
+    if not isinstance(gy, torch.Tensor) or not gy.is_cuda or gy.dtype != torch.float32:
+        raise TypeError("gradient must be a float32 GPU tensor")
+    if gy.dim() != 2 or gy.shape[0] != plan.n_dm or gy.shape[1] < plan.n_samples or gy.stride(1) != 1:
+        raise ValueError("gradient must be [n_dm][>= n_samples] with contiguous rows")
+    if out is None:
+        out = torch.empty((plan.n_channels, plan.input_samples), dtype=torch.float32, device=gy.device)
+    elif (out.dtype != torch.float32 or out.device != gy.device or out.dim() != 2
+          or out.shape[0] != plan.n_channels or out.shape[1] < plan.input_samples or out.stride(1) != 1):
+        raise ValueError("out must be float32 [n_channels][>= input_samples] on the gradient's device")
+    with torch.cuda.device(gy.device):
+        check(_lib.lib().dd_dedisperse_adjoint(plan.handle, ctypes.c_void_p(gy.data_ptr()), gy.stride(0),
+                                               ctypes.c_void_p(out.data_ptr()), out.stride(0),
+                                               _stream_handle(gy.device)))
+    return out
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class Dedisperse(torch.autograd.Function):
+        """y = A x (forward dedispersion); backward applies A^T with the
+        library's adjoint kernel."""
+
+        @staticmethod
+        def forward(ctx, x, plan):
+            ctx.plan = plan
+            ctx.in_shape = tuple(x.shape)
+            ctx.in_dtype = x.dtype
+            return dedisperse(x, plan)
+
+        @staticmethod
+        def backward(ctx, gy):
+            if not ctx.needs_input_grad[0]:
+                return None, None
+            gy = gy.contiguous()
+            gx = dedisperse_adjoint(gy, ctx.plan)
+            if ctx.in_shape[1] != gx.shape[1]:
+                full = torch.zeros(ctx.in_shape, dtype=torch.float32, device=gx.device)
+                full[:, :gx.shape[1]] = gx
+                gx = full
+            return gx.to(ctx.in_dtype), None
+
+    return Dedisperse
+
+
+class _LazyAutograd:
+    _cls = None
+
+    def __getattr__(self, name):
+        if _LazyAutograd._cls is None:
+            _LazyAutograd._cls = _make_autograd()
+        return getattr(_LazyAutograd._cls, name)
+
+
+Dedisperse = _LazyAutograd()
+
+
+class Batch:
+    """Many beams, one persistent launch (see dd_batch_create)."""
+
+    def __init__(self, plans: Sequence[Plan], dtype: int = DD_F32, tune: bool = False, reps: int = 2,
+                 cache_path: Optional[str] = None, device=None):
+        self.plans = list(plans)
+        self.dtype = dtype
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        if tune:
+            cp = cache_path.encode() if cache_path else None
+            check(_lib.lib().dd_batch_autotune(arr, len(self.plans), dtype, int(reps), cp,
+                                               _stream_handle(device)))
+        h = ctypes.c_void_p()
+        check(_lib.lib().dd_batch_create(ctypes.byref(h), arr, len(self.plans), dtype))
+        self._h = h
+        adds = ctypes.c_double()
+        check(_lib.lib().dd_batch_adds(h, ctypes.byref(adds)))
+        self.adds = adds.value
+
+    def run(self, xs, outs=None):
+        torch = _torch()
+        n = len(self.plans)
+        if len(xs) != n:
+            raise ValueError("one input per beam")
+        code = {DD_F32: torch.float32, DD_F16: torch.float16, DD_U8: torch.uint8}[self.dtype]
+        for x, p in zip(xs, self.plans):
+            _check_input(x, p)
+            if x.dtype != code:
+                raise TypeError("batch inputs must all be %s" % code)
+        if outs is None:
+            outs = [torch.empty((p.n_dm, p.n_samples), dtype=torch.float32, device=xs[0].device)
+                    for p in self.plans]
+        ins = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        ins_s = (ctypes.c_int64 * n)(*[x.stride(0) for x in xs])
+        os_ = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
+        os_s = (ctypes.c_int64 * n)(*[o.stride(0) for o in outs])
+        with torch.cuda.device(xs[0].device):
+            check(_lib.lib().dd_batch_run(self._h, ins, ins_s, os_, os_s, _stream_handle(xs[0].device)))
+        return outs
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.lib().dd_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,89 @@
+"""Build libdedisp.so in-tree for gfx950 with hipcc.
+
+    python -m paper_1601_05052_amd.build [-v]
+
+Flags:
+  --offload-arch=gfx950        CDNA4 only; no other targets, no CUDA path
+  -Xclang -target-feature -Xclang -packed-fp32-ops
+                               no v_pk_*_f32 instructions in device code
+  -ffp-contract=off            the host's FP64 delay table is evaluated one
+                               IEEE operation at a time (no FMA contraction)
+"""
+from __future__ import annotations
+
+import glob
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB_NAME = "libdedisp.so"
+
+
+def library_path() -> str:
+    return os.path.join(PKG, LIB_NAME)
+
+
+def hipcc() -> str:
+    for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc"):
+        if c and os.path.exists(c):
+            return c
+    return "hipcc"
+
+
+def sources():
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+
+
+def compile_flags():
+    return ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            "-ffp-contract=off", "-fno-fast-math",
+            "-Wall", "-Wno-unused-function",
+            "-I", INCLUDE, "-I", CSRC]
+
+
+def build(verbose: bool = False, jobs: int = 8) -> str:
+    """Compile every source to an object in _build/ (in parallel) and link."""
+    out_dir = os.path.join(PKG, "_build")
+    os.makedirs(out_dir, exist_ok=True)
+    objs, procs = [], []
+    for src in sources():
+        obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+        objs.append(obj)
+        cmd = [hipcc(), "-c", "-x", "hip"] + compile_flags() + ["-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+        if len(procs) >= jobs:
+            _wait(procs.pop(0), verbose)
+    for p in procs:
+        _wait(p, verbose)
+    lib = library_path()
+    tmp = lib + ".tmp%d" % os.getpid()
+    cmd = [hipcc(), "-shared", "--offload-arch=gfx950", "-o", tmp] + objs
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, lib)
+    return lib
+
+
+def _wait(item, verbose):
+    src, proc = item
+    out, _ = proc.communicate()
+    text = out.decode(errors="replace")
+    # hipcc's host pass does not know the packed-fp32 feature; harmless.
+    lines = [l for l in text.splitlines() if "packed-fp32-ops" not in l]
+    if proc.returncode != 0:
+        sys.stderr.write("\n".join(lines) + "\n")
+        raise RuntimeError("hipcc failed on %s" % src)
+    if verbose and lines:
+        print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,155 @@
+// Internal declarations of libdedisp (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "dedisp.h"
+
+namespace dd {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
+void clear_error();
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+#define DD_HIP_TRY(expr)                                                                   \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return ::dd::fail(DD_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+// ------------------------------------------------------------------ tiles
+//
+// Both directions are one computation, a "shifted-row sum":
+//     out[a][t] = sum_r in[r][t + O[r][a]]    (in[r][g] = 0 outside [0, in_valid))
+// Forward: rows r = channels, accumulator rows a = DMs, O[ch][i] = delay[i][ch].
+// Adjoint: rows r = DMs, accumulator rows a = channels, O[i][ch] = -delay[i][ch].
+// A work-group owns a tile of TA accumulator rows x TT samples.  For each input
+// row it stages the window in[r][t0 + base .. t0 + base + TT + spread) in LDS,
+// where base/spread are the min/range of O[r][.] over the tile.
+
+enum Kind : int32_t {
+    KIND_LDS = 0,     // one LDS read per addition, lanes strided by 64 samples
+    KIND_REGWIN = 1,  // per-lane register window, offsets applied by VGPR index mode
+};
+
+struct Variant {
+    int32_t id;
+    int32_t items_t;    // samples per lane
+    int32_t items_acc;  // accumulator rows per wave
+    int32_t waves;      // wavefronts per work-group
+    int32_t kind;
+    int32_t rpw;        // regwin: input rows per wave per staged chunk
+    int32_t nwr;        // regwin: window registers per lane
+    int32_t kmax;       // regwin: max 64-sample pieces per staged row (wcap <= 64*kmax)
+    int32_t tt() const { return 64 * items_t; }
+    int32_t ta() const { return items_acc * waves; }
+};
+
+const Variant *variants(int32_t *count);
+const Variant *find_variant(int32_t id);
+
+struct SrsArgs {
+    const void *in;
+    int64_t in_stride;
+    int64_t in_valid;
+    float *out;
+    int64_t out_stride;
+    int64_t n_t;
+    int32_t n_acc;
+    int32_t n_rows;
+    const int32_t *rel;    // LDS kind: [n_tiles][n_rows][TA] offsets relative to base
+    const int32_t *base;   // [n_tiles][n_rows] staged-row start relative to the tile's first sample
+    const int32_t *wrec;   // regwin: [n_tiles][n_rows][waves] lane-window start in the staged row
+    const int32_t *woff;   // regwin: [n_tiles][n_rows][waves][items_acc] offsets in the lane window
+    int32_t wcap;          // samples per staged row
+    int32_t rows_per_chunk;
+    int32_t lds_bytes;     // dynamic LDS per work-group
+};
+
+// Element types the kernels read.
+enum InType : int32_t { IN_F32 = DD_F32, IN_F16 = DD_F16, IN_U8 = DD_U8 };
+
+// Launch one shifted-row-sum problem with the given variant.
+hipError_t launch_srs(const Variant &v, int32_t in_type, const SrsArgs &a, hipStream_t stream);
+
+// Host-side layout of one (direction, variant) on one plan.
+struct Layout {
+    bool feasible = false;
+    int32_t n_tiles = 0;
+    int32_t wcap = 0;
+    int32_t rows_per_chunk = 0;
+    int32_t lds_bytes = 0;
+    int32_t max_spread = 0;
+    std::vector<int32_t> base, rel, wrec, woff;
+};
+
+// Device copy of a Layout's tables.
+struct TileTables {
+    int32_t n_tiles = 0;
+    int32_t wcap = 0;
+    int32_t rows_per_chunk = 0;
+    int32_t lds_bytes = 0;
+    int32_t *d_base = nullptr;
+    int32_t *d_rel = nullptr;
+    int32_t *d_wrec = nullptr;
+    int32_t *d_woff = nullptr;
+};
+
+int32_t max_lds_bytes();
+
+}  // namespace dd
+
+struct dd_plan {
+    int32_t C = 0, D = 0;
+    int64_t S = 0;
+    double f_min = 0, df = 0, t_samp = 0, dm_first = 0, dm_step = 0;
+    int32_t max_delay = 0;
+    int64_t T_in = 0;
+    std::vector<int32_t> delay;  // [D][C]
+
+    mutable std::mutex mu;
+    // (device, direction, variant id) -> device tables
+    mutable std::map<std::tuple<int, int, int>, dd::TileTables> tables;
+    // (direction, variant id) -> (feasible, wcap, rows per chunk), host only
+    mutable std::map<std::pair<int, int>, std::tuple<bool, int32_t, int32_t>> fit;
+    // forced tile per (direction, dtype); -1 = automatic
+    int32_t forced[2][3] = {{-1, -1, -1}, {-1, -1, -1}};
+    int32_t tuned[2][3] = {{-1, -1, -1}, {-1, -1, -1}};
+    int32_t tuned_batch[3] = {-1, -1, -1};  // forward, per input type, within the batch family
+};
+
+namespace dd {
+// Compute the layout of (direction, variant); arrays only if build_arrays.
+void compute_layout(const dd_plan *p, int direction, const Variant &v, bool build_arrays, Layout *L);
+// Build (once) and return the device tables for (direction, variant) on the
+// current device.  Returns DD_OK or an error code.
+int plan_tables(const dd_plan *p, int direction, const Variant &v, const TileTables **out);
+// Variant the plan uses for (direction, dtype) when nothing is forced.
+int32_t default_variant(const dd_plan *p, int direction, int32_t in_type);
+// Whether variant v can serve (direction) of this plan (cached, host only).
+bool variant_fits(const dd_plan *p, int direction, const Variant &v);
+int32_t choose_variant(const dd_plan *p, int direction, int32_t in_type);
+// Cost-model choice among `cand` (ids) that fit; -1 if none fits.
+int32_t best_by_model(const dd_plan *p, int direction, const int32_t *cand, int32_t n_cand);
+// The batch kernel's tile family (batch.hip) and the variant a plan uses in it.
+extern const int32_t kBatchFamily[];
+extern const int32_t kBatchFamilySize;
+int32_t batch_slot_of_variant(int32_t v);
+int32_t batch_variant(const dd_plan *p, int32_t in_type);
+// Time the candidates on the plan's own sizes (scratch buffers allocated
+// here); best id and mean ms.  Synchronises the stream.
+int tune_candidates(const dd_plan *p, int direction, int32_t in_type, int32_t reps, const int32_t *cand,
+                    int32_t n_cand, hipStream_t stream, int32_t *best, float *best_ms);
+// Fill SrsArgs for one call (tables built on demand).
+int make_args(const dd_plan *p, int direction, const Variant &v, const void *in, int64_t in_stride,
+              float *out, int64_t out_stride, SrsArgs *a);
+}  // namespace dd

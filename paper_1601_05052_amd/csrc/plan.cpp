@@ -1,0 +1,478 @@
+// Plans: argument checks, the FP64 delay table and the per-tile offset tables.
+//
+// The delay law is Sec. II, Eq. (1) of Sclocco et al.: a channel at f MHz lags
+// the highest frequency f_h by 4150 * DM * (1/f^2 - 1/f_h^2) seconds.  Sampled
+// at t_samp and rounded to the nearest sample (ties to even), this is the
+// delay table that Sec. III-A says is computed ahead of the sums.  This file is
+// compiled with -ffp-contract=off: every binary64 operation below is one IEEE
+// operation in the order written.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+#include <new>
+
+#include "internal.h"
+
+namespace dd {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+const char *last_error() { return g_last_error.c_str(); }
+
+static bool fault_inject_alloc() {
+    const char *e = std::getenv("DD_FAULT_INJECT");
+    return e && std::strcmp(e, "alloc") == 0;
+}
+
+// Delay of channel ch at trial DM i, in samples, before the integer cast.
+static double delay_samples(double f_min, double df, double t_samp, double dm_first,
+                            double dm_step, int32_t C, int32_t i, int32_t ch) {
+    const double f_top = f_min + static_cast<double>(C - 1) * df;  // highest channel
+    const double f = f_min + static_cast<double>(ch) * df;
+    const double dm = dm_first + static_cast<double>(i) * dm_step;
+    const double k = 1.0 / (f * f) - 1.0 / (f_top * f_top);       // MHz^-2
+    return std::rint(((4150.0 * dm) * k) / t_samp);
+}
+
+static inline int32_t offset_of(const dd_plan *p, int direction, int32_t r, int32_t a) {
+    // Forward: O[ch][i] = delay[i][ch]; adjoint: O[i][ch] = -delay[i][ch].
+    return direction == DD_FORWARD ? p->delay[(int64_t)a * p->C + r] : -p->delay[(int64_t)r * p->C + a];
+}
+
+void compute_layout(const dd_plan *p, int direction, const Variant &v, bool build, Layout *L) {
+    const int32_t R = direction == DD_FORWARD ? p->C : p->D;
+    const int32_t A = direction == DD_FORWARD ? p->D : p->C;
+    const int32_t TA = v.ta(), TT = v.tt();
+    const int32_t n_tiles = (A + TA - 1) / TA;
+    *L = Layout();
+    L->n_tiles = n_tiles;
+    if (build) {
+        L->base.resize((size_t)n_tiles * R);
+        if (v.kind == KIND_LDS)
+            L->rel.resize((size_t)n_tiles * R * TA);
+        else {
+            L->wrec.resize((size_t)n_tiles * R * v.waves);
+            L->woff.resize((size_t)n_tiles * R * TA);
+        }
+    }
+    int32_t max_spread = 0;
+    int64_t need = 0;  // regwin: largest staged-row index a lane window touches, + 1
+    bool ok = true;
+    for (int32_t k = 0; k < n_tiles && ok; ++k) {
+        for (int32_t r = 0; r < R && ok; ++r) {
+            int32_t lo = std::numeric_limits<int32_t>::max(), hi = std::numeric_limits<int32_t>::min();
+            for (int32_t j = 0; j < TA; ++j) {
+                const int32_t o = offset_of(p, direction, r, std::min(A - 1, k * TA + j));  // ragged tile repeats its last row
+                lo = std::min(lo, o);
+                hi = std::max(hi, o);
+            }
+            max_spread = std::max(max_spread, hi - lo);
+            if (build)
+                L->base[(size_t)k * R + r] = lo;
+            if (v.kind == KIND_LDS) {
+                if (build)
+                    for (int32_t j = 0; j < TA; ++j)
+                        L->rel[((size_t)k * R + r) * TA + j] = offset_of(p, direction, r, std::min(A - 1, k * TA + j)) - lo;
+                continue;
+            }
+            const int32_t TDW = v.items_acc;
+            const int32_t S = v.items_t / 4;  // window quads per lane step (see regwin_asm.h)
+            const int32_t align = 4 * S;      // window starts on multiples of S quads
+            for (int32_t w = 0; w < v.waves; ++w) {
+                int32_t wmin = std::numeric_limits<int32_t>::max(), wmax = 0;
+                for (int32_t j = 0; j < TDW; ++j) {
+                    const int32_t o = offset_of(p, direction, r, std::min(A - 1, k * TA + w * TDW + j)) - lo;
+                    wmin = std::min(wmin, o);
+                    wmax = std::max(wmax, o);
+                }
+                const int32_t ws = wmin - wmin % align;
+                const int32_t nq = (wmax - ws + v.items_t + 3) / 4;
+                if (4 * nq > v.nwr) {
+                    ok = false;  // this wave's delays spread wider than its register window
+                    break;
+                }
+                need = std::max<int64_t>(need, (int64_t)63 * v.items_t + ws + 4 * nq);
+                if (build) {
+                    const int32_t c = ws / 4;
+                    const int32_t u_bytes = 16 * (S == 1 ? c : c + c / S);  // padded LDS layout
+                    L->wrec[((size_t)k * R + r) * v.waves + w] = u_bytes | (nq << 20);
+                    for (int32_t j = 0; j < TDW; ++j)
+                        L->woff[(((size_t)k * R + r) * v.waves + w) * TDW + j] =
+                            offset_of(p, direction, r, std::min(A - 1, k * TA + w * TDW + j)) - lo - ws;
+                }
+            }
+        }
+    }
+    L->max_spread = max_spread;
+    if (!ok)
+        return;
+    const int64_t lds_limit = 160 * 1024;
+    if (v.kind == KIND_LDS) {
+        const int64_t w4 = ((int64_t)TT + max_spread + 3) & ~int64_t(3);
+        const int64_t row_bytes = w4 * 4;
+        if (row_bytes > lds_limit)
+            return;
+        int64_t rpc = (64 * 1024) / row_bytes;  // leave room for two or more work-groups per CU
+        rpc = std::max<int64_t>(1, std::min<int64_t>(rpc, 32));
+        L->wcap = (int32_t)w4;
+        L->rows_per_chunk = (int32_t)rpc;
+        L->lds_bytes = (int32_t)(rpc * row_bytes);
+    } else {
+        const int64_t w64 = (std::max<int64_t>(need, (int64_t)TT + max_spread) + 63) & ~int64_t(63);
+        if (w64 > (int64_t)64 * v.kmax)
+            return;
+        const int64_t rows = (int64_t)v.waves * v.rpw;
+        const int64_t S = v.items_t / 4;
+        const int64_t row_dw = S == 1 ? w64 : w64 / S * (S + 1);  // padded layout
+        if (rows * row_dw * 4 > lds_limit || (need >> 20) != 0)
+            return;
+        L->wcap = (int32_t)w64;
+        L->rows_per_chunk = (int32_t)rows;
+        L->lds_bytes = (int32_t)(rows * row_dw * 4);
+    }
+    L->feasible = true;
+}
+
+bool variant_fits(const dd_plan *p, int direction, const Variant &v) {
+    {
+        std::lock_guard<std::mutex> lock(p->mu);
+        auto it = p->fit.find({direction, v.id});
+        if (it != p->fit.end())
+            return std::get<0>(it->second);
+    }
+    Layout L;
+    compute_layout(p, direction, v, false, &L);
+    std::lock_guard<std::mutex> lock(p->mu);
+    p->fit[{direction, v.id}] = std::make_tuple(L.feasible, L.wcap, L.rows_per_chunk);
+    return L.feasible;
+}
+
+static int upload(const std::vector<int32_t> &h, int32_t **d) {
+    *d = nullptr;
+    if (h.empty())
+        return DD_OK;
+    if (hipMalloc(d, h.size() * sizeof(int32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        *d = nullptr;
+        return fail(DD_ENOMEM, "device allocation of %zu table entries failed", h.size());
+    }
+    hipError_t e = hipMemcpy(*d, h.data(), h.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess)
+        return fail(DD_EHIP, "upload of tile tables failed: %s", hipGetErrorString(e));
+    return DD_OK;
+}
+
+static void free_tables(TileTables &t) {
+    (void)hipFree(t.d_base);
+    (void)hipFree(t.d_rel);
+    (void)hipFree(t.d_wrec);
+    (void)hipFree(t.d_woff);
+    t = TileTables();
+}
+
+int plan_tables(const dd_plan *p, int direction, const Variant &v, const TileTables **out) {
+    int dev = 0;
+    DD_HIP_TRY(hipGetDevice(&dev));
+    const auto key = std::make_tuple(dev, direction, (int)v.id);
+    {
+        std::lock_guard<std::mutex> lock(p->mu);
+        auto it = p->tables.find(key);
+        if (it != p->tables.end()) {
+            *out = &it->second;
+            return DD_OK;
+        }
+    }
+    Layout L;
+    try {
+        compute_layout(p, direction, v, true, &L);
+    } catch (const std::bad_alloc &) {
+        return fail(DD_ENOMEM, "host allocation of tile tables failed");
+    }
+    if (!L.feasible)
+        return fail(DD_EUNSUPPORTED, "tile variant %d cannot serve this plan (delay spread too wide)", v.id);
+    if (fault_inject_alloc())
+        return fail(DD_ENOMEM, "device allocation of tile tables failed (DD_FAULT_INJECT=alloc)");
+    TileTables t;
+    t.n_tiles = L.n_tiles;
+    t.wcap = L.wcap;
+    t.rows_per_chunk = L.rows_per_chunk;
+    t.lds_bytes = L.lds_bytes;
+    int rc = upload(L.base, &t.d_base);
+    if (rc == DD_OK)
+        rc = upload(L.rel, &t.d_rel);
+    if (rc == DD_OK)
+        rc = upload(L.wrec, &t.d_wrec);
+    if (rc == DD_OK)
+        rc = upload(L.woff, &t.d_woff);
+    if (rc != DD_OK) {
+        free_tables(t);
+        return rc;
+    }
+    std::lock_guard<std::mutex> lock(p->mu);
+    auto ins = p->tables.emplace(key, t);
+    if (!ins.second)
+        free_tables(t);  // another thread built it first
+    *out = &ins.first->second;
+    return DD_OK;
+}
+
+// Rough time model for choosing a variant without measuring it: additions at
+// the kind's sustained rate plus staged input samples at an L2-to-LDS rate
+// (both measured on MI355X; the auto-tuner replaces this with timings).
+static double estimate_seconds(const dd_plan *p, int direction, const Variant &v, int32_t wcap) {
+    const double adds = static_cast<double>(p->D) * static_cast<double>(p->S) * p->C;
+    const int32_t R = direction == DD_FORWARD ? p->C : p->D;
+    const int32_t A = direction == DD_FORWARD ? p->D : p->C;
+    const int64_t n_t = direction == DD_FORWARD ? p->S : p->T_in;
+    const double tiles = static_cast<double>((n_t + v.tt() - 1) / v.tt()) * ((A + v.ta() - 1) / v.ta());
+    const double staged = tiles * R * static_cast<double>(wcap);
+    const double add_rate = v.kind == KIND_REGWIN ? 30e12 : 6e12;
+    return adds / add_rate + staged / 0.8e12;
+}
+
+int32_t best_by_model(const dd_plan *p, int direction, const int32_t *cand, int32_t n_cand) {
+    int32_t best = -1;
+    double best_t = 0.0;
+    for (int32_t i = 0; i < n_cand; ++i) {
+        const Variant *v = find_variant(cand[i]);
+        if (!v || !variant_fits(p, direction, *v))
+            continue;
+        int32_t wcap = 0;
+        {
+            std::lock_guard<std::mutex> lock(p->mu);
+            wcap = std::get<1>(p->fit[{direction, v->id}]);
+        }
+        const double t = estimate_seconds(p, direction, *v, wcap);
+        if (best < 0 || t < best_t) {
+            best = v->id;
+            best_t = t;
+        }
+    }
+    return best;
+}
+
+int32_t default_variant(const dd_plan *p, int direction, int32_t in_type) {
+    (void)in_type;
+    int32_t n = 0;
+    variants(&n);
+    std::vector<int32_t> all(n);
+    for (int32_t i = 0; i < n; ++i)
+        all[i] = i;
+    return best_by_model(p, direction, all.data(), n);
+}
+
+int32_t batch_variant(const dd_plan *p, int32_t in_type) {
+    int32_t pick[2];
+    {
+        std::lock_guard<std::mutex> lock(p->mu);
+        pick[0] = p->tuned_batch[in_type];
+        pick[1] = p->forced[DD_FORWARD][in_type] >= 0 ? p->forced[DD_FORWARD][in_type]
+                                                       : p->tuned[DD_FORWARD][in_type];
+    }
+    for (int32_t id : pick)
+        if (id >= 0 && batch_slot_of_variant(id) >= 0 && variant_fits(p, DD_FORWARD, *find_variant(id)))
+            return id;
+    return best_by_model(p, DD_FORWARD, kBatchFamily, kBatchFamilySize);
+}
+
+int32_t choose_variant(const dd_plan *p, int direction, int32_t in_type) {
+    std::lock_guard<std::mutex> lock(p->mu);
+    if (p->forced[direction][in_type] >= 0)
+        return p->forced[direction][in_type];
+    if (p->tuned[direction][in_type] >= 0)
+        return p->tuned[direction][in_type];
+    return -2;  // caller computes the default outside the lock
+}
+
+int make_args(const dd_plan *p, int direction, const Variant &v, const void *in, int64_t in_stride,
+              float *out, int64_t out_stride, SrsArgs *a) {
+    const TileTables *t = nullptr;
+    int rc = plan_tables(p, direction, v, &t);
+    if (rc != DD_OK)
+        return rc;
+    a->in = in;
+    a->in_stride = in_stride;
+    a->out = out;
+    a->out_stride = out_stride;
+    if (direction == DD_FORWARD) {
+        a->in_valid = p->T_in;
+        a->n_t = p->S;
+        a->n_acc = p->D;
+        a->n_rows = p->C;
+    } else {
+        a->in_valid = p->S;
+        a->n_t = p->T_in;
+        a->n_acc = p->C;
+        a->n_rows = p->D;
+    }
+    a->rel = t->d_rel;
+    a->base = t->d_base;
+    a->wrec = t->d_wrec;
+    a->woff = t->d_woff;
+    a->wcap = t->wcap;
+    a->rows_per_chunk = t->rows_per_chunk;
+    a->lds_bytes = t->lds_bytes;
+    return DD_OK;
+}
+
+}  // namespace dd
+
+using namespace dd;
+
+extern "C" {
+
+int dd_plan_create(dd_plan **out, int32_t n_channels, double f_min_mhz, double df_mhz,
+                   double t_samp_s, double dm_first, double dm_step, int32_t n_dm,
+                   int64_t n_samples) {
+    clear_error();
+    if (!out)
+        return fail(DD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n_channels < 1)
+        return fail(DD_EINVAL, "n_channels must be >= 1 (got %d)", n_channels);
+    if (n_dm < 1)
+        return fail(DD_EINVAL, "n_dm must be >= 1 (got %d)", n_dm);
+    if (n_samples < 1)
+        return fail(DD_EINVAL, "n_samples must be >= 1 (got %lld)", (long long)n_samples);
+    const double vals[] = {f_min_mhz, df_mhz, t_samp_s, dm_first, dm_step};
+    for (double v : vals)
+        if (!std::isfinite(v))
+            return fail(DD_EINVAL, "plan parameters must be finite");
+    if (!(f_min_mhz > 0.0))
+        return fail(DD_EINVAL, "f_min_mhz must be > 0 (got %g)", f_min_mhz);
+    if (!(df_mhz > 0.0))
+        return fail(DD_EINVAL, "df_mhz must be > 0 (got %g)", df_mhz);
+    if (!(t_samp_s > 0.0))
+        return fail(DD_EINVAL, "t_samp_s must be > 0 (got %g)", t_samp_s);
+    if (dm_first < 0.0)
+        return fail(DD_EINVAL, "dm_first must be >= 0 (got %g)", dm_first);
+    if (dm_step < 0.0)
+        return fail(DD_EINVAL, "dm_step must be >= 0 (got %g)", dm_step);
+    if (!std::isfinite(f_min_mhz + static_cast<double>(n_channels - 1) * df_mhz) ||
+        !std::isfinite(dm_first + static_cast<double>(n_dm - 1) * dm_step))
+        return fail(DD_EINVAL, "frequency or DM range overflows");
+
+    dd_plan *p = nullptr;
+    try {
+        p = new dd_plan();
+        p->delay.resize((size_t)n_dm * n_channels);
+    } catch (const std::bad_alloc &) {
+        delete p;
+        return fail(DD_ENOMEM, "host allocation of the delay table failed");
+    }
+    p->C = n_channels;
+    p->D = n_dm;
+    p->S = n_samples;
+    p->f_min = f_min_mhz;
+    p->df = df_mhz;
+    p->t_samp = t_samp_s;
+    p->dm_first = dm_first;
+    p->dm_step = dm_step;
+    int32_t maxd = 0;
+    for (int32_t i = 0; i < n_dm; ++i) {
+        for (int32_t ch = 0; ch < n_channels; ++ch) {
+            const double r = delay_samples(f_min_mhz, df_mhz, t_samp_s, dm_first, dm_step, n_channels, i, ch);
+            if (!(r >= 0.0 && r <= 2147483647.0)) {
+                delete p;
+                return fail(DD_EINVAL, "delay of DM index %d, channel %d (%g samples) does not fit int32", i,
+                            ch, r);
+            }
+            const int32_t d = static_cast<int32_t>(r);
+            p->delay[(size_t)i * n_channels + ch] = d;
+            maxd = std::max(maxd, d);
+        }
+    }
+    p->max_delay = maxd;
+    p->T_in = n_samples + maxd;
+    if (p->T_in >= (int64_t(1) << 29)) {
+        delete p;
+        return fail(DD_EINVAL, "n_samples + max delay must be below 2^29 samples");
+    }
+    *out = p;
+    return DD_OK;
+}
+
+int dd_plan_destroy(dd_plan *p) {
+    clear_error();
+    if (!p)
+        return DD_OK;
+    int cur = 0;
+    bool have_dev = hipGetDevice(&cur) == hipSuccess;
+    for (auto &kv : p->tables) {
+        const int dev = std::get<0>(kv.first);
+        if (have_dev)
+            (void)hipSetDevice(dev);
+        free_tables(kv.second);
+    }
+    if (have_dev)
+        (void)hipSetDevice(cur);
+    delete p;
+    return DD_OK;
+}
+
+int dd_plan_dims(const dd_plan *p, int32_t *n_channels, int32_t *n_dm, int64_t *n_samples) {
+    clear_error();
+    if (!p)
+        return fail(DD_EINVAL, "plan is NULL");
+    if (n_channels)
+        *n_channels = p->C;
+    if (n_dm)
+        *n_dm = p->D;
+    if (n_samples)
+        *n_samples = p->S;
+    return DD_OK;
+}
+
+int dd_plan_max_delay(const dd_plan *p, int32_t *out) {
+    clear_error();
+    if (!p || !out)
+        return fail(DD_EINVAL, "NULL argument");
+    *out = p->max_delay;
+    return DD_OK;
+}
+
+int dd_plan_input_samples(const dd_plan *p, int64_t *out) {
+    clear_error();
+    if (!p || !out)
+        return fail(DD_EINVAL, "NULL argument");
+    *out = p->T_in;
+    return DD_OK;
+}
+
+int dd_plan_delay_table(const dd_plan *p, int32_t *host_dst) {
+    clear_error();
+    if (!p || !host_dst)
+        return fail(DD_EINVAL, "NULL argument");
+    std::memcpy(host_dst, p->delay.data(), p->delay.size() * sizeof(int32_t));
+    return DD_OK;
+}
+
+const char *dd_last_error(void) { return dd::last_error(); }
+
+const char *dd_version(void) { return "libdedisp 0.1 (gfx950)"; }
+
+}  // extern "C"

@@ -1,0 +1,166 @@
+// Shifted-row-sum kernels for gfx950 (CDNA4), used by both directions:
+//     out[a][t] = sum_r in[r][t + O[r][a]]
+// (forward dedispersion, Sec. III-A Algorithm 1, with rows = channels and
+// accumulator rows = trial DMs; the adjoint with rows = DMs, accumulator rows =
+// channels and O = -delay).
+//
+// Decomposition follows Sec. III-B: DM (accumulator) and time are the
+// independent axes; a work-group owns TA accumulator rows x TT consecutive
+// samples, lanes run along time so stores are coalesced and aligned, each
+// lane keeps its outputs in registers, and the work-group stages each input
+// row's window in LDS once so every accumulator row of the tile reuses it
+// (the data reuse of Sec. III-A, Eq. (3)).  Only binary32 additions; no MFMA.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "srs_regwin.h"
+#include "srs_tile.h"
+
+namespace dd {
+
+namespace {
+
+using dev::SrsDims;
+
+template <typename TIn, int IT, int TDW, int NW>
+__global__ void __launch_bounds__(64 * NW)
+    srs_lds_kernel(const TIn *__restrict__ in, float *__restrict__ out, const int32_t *__restrict__ rel,
+                   const int32_t *__restrict__ base, SrsDims d) {
+    extern __shared__ float lds[];
+    int32_t tile_t, tile_a;
+    dev::tile_of_block(d, tile_t, tile_a);
+    dev::srs_tile_lds<TIn, IT, TDW, NW>(in, out, rel, base, d, tile_t, tile_a, lds);
+}
+
+template <typename TIn, int IT, int TDW, int NW, int RPW, int KMAX>
+__global__ void __launch_bounds__(64 * NW)
+    srs_regwin_kernel(const TIn *__restrict__ in, float *__restrict__ out, const int32_t *__restrict__ base,
+                      const int32_t *__restrict__ wrec, const int32_t *__restrict__ woff, SrsDims d) {
+    extern __shared__ __attribute__((aligned(16))) float lds_rw[];
+    int32_t tile_t, tile_a;
+    dev::tile_of_block(d, tile_t, tile_a);
+    dev::srs_tile_regwin<TIn, IT, TDW, NW, RPW, KMAX>(in, out, base, wrec, woff, d, tile_t, tile_a, lds_rw);
+}
+
+using LaunchFn = hipError_t (*)(const SrsArgs &, const SrsDims &, uint32_t, size_t, hipStream_t);
+
+hipError_t set_lds_limit(const void *fn, size_t lds) {
+    if (lds <= 65536)
+        return hipSuccess;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+}
+
+template <typename TIn, int IT, int TDW, int NW>
+hipError_t launch_lds(const SrsArgs &a, const SrsDims &d, uint32_t blocks, size_t lds, hipStream_t s) {
+    auto fn = srs_lds_kernel<TIn, IT, TDW, NW>;
+    hipError_t e = set_lds_limit(reinterpret_cast<const void *>(fn), lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * NW), lds, s, static_cast<const TIn *>(a.in), a.out, a.rel,
+                       a.base, d);
+    return hipGetLastError();
+}
+
+template <typename TIn, int IT, int TDW, int NW, int RPW, int KMAX>
+hipError_t launch_regwin(const SrsArgs &a, const SrsDims &d, uint32_t blocks, size_t lds, hipStream_t s) {
+    auto fn = srs_regwin_kernel<TIn, IT, TDW, NW, RPW, KMAX>;
+    hipError_t e = set_lds_limit(reinterpret_cast<const void *>(fn), lds);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * NW), lds, s, static_cast<const TIn *>(a.in), a.out, a.base,
+                       a.wrec, a.woff, d);
+    return hipGetLastError();
+}
+
+struct VariantImpl {
+    Variant v;
+    LaunchFn fn[3];  // by input type: f32, f16, u8
+};
+
+#define DD_LDS_VARIANT(ID, IT, TDW, NW)                                                   \
+    {{ID, IT, TDW, NW, KIND_LDS, 0, 0, 0},                                                \
+     {launch_lds<float, IT, TDW, NW>, launch_lds<_Float16, IT, TDW, NW>, launch_lds<uint8_t, IT, TDW, NW>}}
+
+#define DD_RW_VARIANT(ID, IT, TDW, NW, RPW, KMAX)                                                 \
+    {{ID, IT, TDW, NW, KIND_REGWIN, RPW, dev::RegWin<IT, TDW>::NWR, KMAX},                        \
+     {launch_regwin<float, IT, TDW, NW, RPW, KMAX>, launch_regwin<_Float16, IT, TDW, NW, RPW, KMAX>, \
+      launch_regwin<uint8_t, IT, TDW, NW, RPW, KMAX>}}
+
+const VariantImpl kImpls[] = {
+    DD_LDS_VARIANT(0, 4, 8, 4),   // 256 samples x 32 rows
+    DD_LDS_VARIANT(1, 4, 4, 4),   // 256 x 16
+    DD_LDS_VARIANT(2, 2, 8, 4),   // 128 x 32
+    DD_LDS_VARIANT(3, 8, 4, 4),   // 512 x 16
+    DD_LDS_VARIANT(4, 4, 16, 4),  // 256 x 64
+    DD_LDS_VARIANT(5, 2, 16, 4),  // 128 x 64
+    DD_LDS_VARIANT(6, 4, 2, 4),   // 256 x 8
+    DD_LDS_VARIANT(7, 4, 1, 4),   // 256 x 4
+    DD_LDS_VARIANT(8, 2, 1, 4),   // 128 x 4
+    DD_LDS_VARIANT(9, 1, 1, 1),   // 64 x 1: no cross-row window, always fits
+    DD_RW_VARIANT(10, 8, 8, 4, 1, 16),   // 512 x 32, register window
+    DD_RW_VARIANT(11, 8, 8, 4, 2, 16),   // 512 x 32, two rows per wave per chunk
+    DD_RW_VARIANT(12, 8, 4, 4, 2, 16),   // 512 x 16
+    DD_RW_VARIANT(13, 16, 4, 4, 1, 24),  // 1024 x 16
+    DD_RW_VARIANT(14, 4, 8, 4, 2, 12),   // 256 x 32
+    DD_RW_VARIANT(15, 8, 8, 8, 1, 16),   // 512 x 64, eight waves
+    DD_RW_VARIANT(16, 8, 16, 4, 1, 16),  // 512 x 64, sixteen rows per wave
+    DD_RW_VARIANT(17, 8, 8, 4, 1, 12),   // 512 x 32, shorter staging (fewer VGPRs)
+};
+constexpr int32_t kNumImpls = sizeof(kImpls) / sizeof(kImpls[0]);
+
+Variant g_variants[kNumImpls];
+bool g_variants_init = false;
+
+}  // namespace
+
+const Variant *variants(int32_t *count) {
+    if (!g_variants_init) {
+        for (int32_t i = 0; i < kNumImpls; ++i)
+            g_variants[i] = kImpls[i].v;
+        g_variants_init = true;
+    }
+    *count = kNumImpls;
+    return g_variants;
+}
+
+const Variant *find_variant(int32_t id) {
+    int32_t n = 0;
+    const Variant *vs = variants(&n);
+    return (id >= 0 && id < n) ? &vs[id] : nullptr;
+}
+
+int32_t max_lds_bytes() {
+    static int32_t cached = 0;
+    if (!cached) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+            cached = v;
+        else
+            cached = 160 * 1024;  // gfx950
+    }
+    return cached;
+}
+
+hipError_t launch_srs(const Variant &v, int32_t in_type, const SrsArgs &a, hipStream_t stream) {
+    const VariantImpl &impl = kImpls[v.id];
+    SrsDims d;
+    d.in_stride = a.in_stride;
+    d.in_valid = a.in_valid;
+    d.out_stride = a.out_stride;
+    d.n_t = a.n_t;
+    d.n_acc = a.n_acc;
+    d.n_rows = a.n_rows;
+    d.wcap = a.wcap;
+    d.rows_per_chunk = a.rows_per_chunk;
+    d.n_t_tiles = static_cast<int32_t>((a.n_t + v.tt() - 1) / v.tt());
+    d.n_acc_tiles = (a.n_acc + v.ta() - 1) / v.ta();
+    const uint64_t blocks = static_cast<uint64_t>(d.n_t_tiles) * d.n_acc_tiles;
+    if (blocks == 0)
+        return hipSuccess;
+    if (blocks > 0x7fffffffull)
+        return hipErrorInvalidConfiguration;
+    return impl.fn[in_type](a, d, static_cast<uint32_t>(blocks), static_cast<size_t>(a.lds_bytes), stream);
+}
+
+}  // namespace dd

@@ -1,0 +1,202 @@
+// Register-window tile routine (gfx950) for the shifted-row sum
+//     out[a][t] = sum_r in[r][t + O[r][a]].
+//
+// Same decomposition as the LDS form (Sec. III-B: DM x time work-groups,
+// several outputs per work-item kept in registers, input rows staged once per
+// work-group in LDS), but each lane owns IT *consecutive* samples and copies
+// the part of the staged row it needs -- IT + (spread of its wave's
+// accumulator rows) samples -- into VGPRs once per input row.  Every
+// accumulator row then adds that register window at its own wave-uniform
+// offset through VGPR index mode (see regwin_asm.h): one VALU addition per
+// output element and one LDS word per ~IT*TDW/(IT+spread) additions, instead
+// of one LDS word per addition.  This is the data reuse of Sec. III-A, Eq. (3)
+// moved from local memory into registers.
+//
+// Staging: every wave owns RPW rows of each chunk of NW*RPW input rows.  Its
+// lanes fetch them with bounds-checked buffer loads (samples outside
+// [0, in_valid) read as zero), one chunk ahead, into registers; after the
+// chunk is consumed they are written to LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "regwin_asm.h"
+#include "srs_tile.h"
+
+namespace dd {
+namespace dev {
+
+constexpr uint32_t kBufferFlags = 0x00020000u;  // raw buffer, 32-bit data format (gfx9 V# word 3)
+constexpr uint32_t kOutOfRange = 0x80000000u;   // any offset >= num_records reads 0
+
+template <typename TIn>
+__device__ __forceinline__ float buffer_ld(__amdgpu_buffer_rsrc_t rs, uint32_t byte_off);
+template <>
+__device__ __forceinline__ float buffer_ld<float>(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, off, 0, 0));
+}
+template <>
+__device__ __forceinline__ float buffer_ld<_Float16>(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    return static_cast<float>(__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(rs, off, 0, 0)));
+}
+template <>
+__device__ __forceinline__ float buffer_ld<uint8_t>(__amdgpu_buffer_rsrc_t rs, uint32_t off) {
+    return static_cast<float>(__builtin_amdgcn_raw_buffer_load_b8(rs, off, 0, 0));
+}
+
+// Fetch samples [g0, g0 + 64*nk) of input row `row` into pre[]: lane l gets
+// samples g0 + l + 64k for k < KMAX.  The buffer's range is clipped to
+// min(in_valid, g0 + 64*nk), so every sample outside the row or past the
+// window reads zero and the loads need no per-lane conditions (which would
+// otherwise force a wait on each load).
+template <typename TIn, int KMAX>
+__device__ __forceinline__ void fetch_row(const TIn *__restrict__ in, int64_t in_stride, int64_t in_valid,
+                                          int32_t row, int64_t g0, int32_t nk, int lane, float (&pre)[KMAX]) {
+    const TIn *rp = in + static_cast<int64_t>(row) * in_stride;
+    const int64_t end = min(in_valid, g0 + 64 * static_cast<int64_t>(nk));
+    const int32_t n_bytes = end > 0 ? static_cast<int32_t>(end * static_cast<int64_t>(sizeof(TIn))) : 0;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<TIn *>(rp), 0, n_bytes, kBufferFlags);
+    if (g0 >= 0) {
+        // g0 < 2^29 keeps every offset below 2^31.
+        const uint32_t voff = static_cast<uint32_t>(g0 + lane) * sizeof(TIn);
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+            pre[k] = buffer_ld<TIn>(rs, voff + k * 64 * sizeof(TIn));
+    } else {
+        // Window starts before sample 0 (adjoint near t = 0): lanes whose sample
+        // index is negative read out of range, i.e. zero.
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) {
+            const int64_t g = g0 + lane + 64 * k;
+            const uint32_t off = g >= 0 ? static_cast<uint32_t>(g) * sizeof(TIn) : kOutOfRange;
+            pre[k] = buffer_ld<TIn>(rs, off);
+        }
+    }
+}
+
+// 32-bit LDS address of a pointer into __shared__ memory.
+__device__ __forceinline__ uint32_t lds_address(const float *p) {
+    return static_cast<uint32_t>(reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) float *)p));
+}
+
+template <typename TIn, int IT, int TDW, int NW, int RPW, int KMAX>
+__device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, float *__restrict__ out,
+                                                const int32_t *__restrict__ base,
+                                                const int32_t *__restrict__ wrec,
+                                                const int32_t *__restrict__ woff, const SrsDims &d,
+                                                int32_t tile_t, int32_t tile_a, float *lds) {
+    using RW = RegWin<IT, TDW>;
+    constexpr int TT = 64 * IT;
+    constexpr int TA = TDW * NW;
+    constexpr int CR = NW * RPW;  // input rows per chunk
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t t0 = static_cast<int64_t>(tile_t) * TT;
+    const int32_t *base_tile = base + static_cast<int64_t>(tile_a) * d.n_rows;
+    const int32_t *wrec_tile = wrec + static_cast<int64_t>(tile_a) * d.n_rows * NW + wave;
+    const int32_t *woff_tile = woff + (static_cast<int64_t>(tile_a) * d.n_rows * NW + wave) * TDW;
+    const int32_t nk = d.wcap >> 6;  // wcap is a multiple of 64
+
+    typename RW::Acc acc;
+#pragma unroll
+    for (int i = 0; i < IT * TDW; ++i)
+        RW::set_acc(acc, i, 0.f);
+
+    float pre[RPW][KMAX];
+    const int32_t n_chunks = (d.n_rows + CR - 1) / CR;
+#pragma unroll
+    for (int q = 0; q < RPW; ++q) {
+        const int32_t row = wave * RPW + q;
+        if (row < d.n_rows)
+            fetch_row<TIn, KMAX>(in, d.in_stride, d.in_valid, row, t0 + base_tile[row], nk, lane, pre[q]);
+    }
+
+    // Padded LDS row layout (see regwin_asm.h): logical quad Q at physical
+    // quad Q + floor(Q/S) (no padding when S == 1).
+    constexpr int S = RW::S;
+    const int32_t row_dw = S == 1 ? d.wcap : d.wcap / S * (S + 1);  // physical dwords per row
+    const int32_t lane_st = S == 1 ? lane : 4 * ((lane >> 2) + ((lane >> 2) / S)) + (lane & 3);
+    constexpr int32_t piece_dw = S == 1 ? 64 : 64 / S * (S + 1);       // physical dwords per 64 samples
+    const uint32_t lds_base = lds_address(lds);
+    const uint32_t lane_rd = lds_base + static_cast<uint32_t>(lane) * 16u * (S == 1 ? 1u : S + 1u);
+
+    for (int32_t c = 0; c < n_chunks; ++c) {
+        const int32_t r0 = c * CR;
+        __syncthreads();  // every wave has finished reading the previous chunk
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+            const int32_t rr = wave * RPW + q;
+            if (r0 + rr < d.n_rows) {
+                float *dst = lds + rr * row_dw + lane_st;
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k)
+                    if (k < nk)
+                        dst[piece_dw * k] = pre[q][k];
+            }
+        }
+        __syncthreads();  // chunk c is staged
+        if (c + 1 < n_chunks) {
+#pragma unroll
+            for (int q = 0; q < RPW; ++q) {
+                const int32_t row = r0 + CR + wave * RPW + q;
+                if (row < d.n_rows)
+                    fetch_row<TIn, KMAX>(in, d.in_stride, d.in_valid, row, t0 + base_tile[row], nk, lane, pre[q]);
+            }
+        }
+        const int32_t nr = min(CR, d.n_rows - r0);
+        // Window records and offsets of this wave's accumulator rows for the chunk.
+        int rec[CR];
+        int o[CR][TDW];
+#pragma unroll
+        for (int rr = 0; rr < CR; ++rr) {
+            const int32_t r = min(r0 + rr, d.n_rows - 1);
+            // Wave-uniform by construction; readfirstlane keeps them in SGPRs
+            // for the assembly even where the compiler cannot prove it.
+            rec[rr] = __builtin_amdgcn_readfirstlane(wrec_tile[static_cast<int64_t>(r) * NW]);
+#pragma unroll
+            for (int a = 0; a < TDW; ++a)
+                o[rr][a] = __builtin_amdgcn_readfirstlane(woff_tile[static_cast<int64_t>(r) * NW * TDW + a]);
+        }
+        auto addr_of = [&](int rr) {
+            return lane_rd + static_cast<uint32_t>(rr * row_dw) * 4u + static_cast<uint32_t>(rec[rr] & 0xfffff);
+        };
+#pragma unroll
+        for (int rr = 0; rr < CR; ++rr) {
+            if (rr >= nr)
+                break;
+            RW::row(acc, addr_of(rr), rec[rr] >> 20, o[rr]);
+        }
+    }
+
+    const int64_t tl = t0 + static_cast<int64_t>(lane) * IT;
+#pragma unroll
+    for (int a = 0; a < TDW; ++a) {
+        const int32_t ag = tile_a * TA + wave * TDW + a;
+        if (ag >= d.n_acc)
+            break;
+        float *dst = out + static_cast<int64_t>(ag) * d.out_stride + tl;
+        const bool vec = (reinterpret_cast<uintptr_t>(dst) & 15) == 0;
+        if (tl + IT <= d.n_t && vec) {
+#pragma unroll
+            for (int j = 0; j < IT; j += 4) {
+                v4f v;
+                v.x = RW::get_acc(acc, a * IT + j + 0);
+                v.y = RW::get_acc(acc, a * IT + j + 1);
+                v.z = RW::get_acc(acc, a * IT + j + 2);
+                v.w = RW::get_acc(acc, a * IT + j + 3);
+                __builtin_nontemporal_store(v, reinterpret_cast<v4f *>(dst + j));
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < IT; ++j)
+                if (tl + j < d.n_t)
+                    dst[j] = RW::get_acc(acc, a * IT + j);
+        }
+    }
+}
+
+}  // namespace dev
+}  // namespace dd

@@ -1,0 +1,212 @@
+// Auto-tuning of the tile shape (Sclocco et al., Sec. IV-A): run every tile
+// variant that can serve the plan, on the plan's own sizes, and keep the
+// fastest.  Results can be cached in a text file keyed by device, direction,
+// input type and plan shape ("no single optimal configuration" exists across
+// setups and instances, Sec. V-A, so the key includes the whole setup).
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace dd {
+int run_direction(const dd_plan *p, int direction, int32_t in_type, const Variant &v, const void *in,
+                  int64_t in_stride, float *out, int64_t out_stride, hipStream_t stream);
+}
+
+using namespace dd;
+
+namespace {
+
+std::string cache_key(const dd_plan *p, int direction, int32_t in_type) {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    std::memset(&prop, 0, sizeof(prop));
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipGetDeviceProperties(&prop, dev);
+    char buf[512];
+    std::snprintf(buf, sizeof(buf), "%s|cu%d|dir%d|dt%d|C%d|D%d|S%lld|%.17g|%.17g|%.17g|%.17g|%.17g|v1",
+                  prop.gcnArchName, prop.multiProcessorCount, direction, in_type, p->C, p->D,
+                  (long long)p->S, p->f_min, p->df, p->t_samp, p->dm_first, p->dm_step);
+    for (char *c = buf; *c; ++c)
+        if (*c == ' ')
+            *c = '_';
+    return buf;
+}
+
+bool cache_lookup(const char *path, const std::string &key, int32_t *variant, float *ms) {
+    std::ifstream f(path);
+    if (!f)
+        return false;
+    std::string line;
+    bool found = false;
+    while (std::getline(f, line)) {
+        std::istringstream ss(line);
+        std::string k;
+        int32_t v;
+        float t;
+        if (ss >> k >> v >> t && k == key && find_variant(v)) {
+            *variant = v;
+            *ms = t;
+            found = true;  // last entry wins
+        }
+    }
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, int32_t variant, float ms) {
+    std::ofstream f(path, std::ios::app);
+    if (f)
+        f << key << ' ' << variant << ' ' << ms << '\n';
+}
+
+}  // namespace
+
+namespace dd {
+
+int tune_candidates(const dd_plan *p, int direction, int32_t in_type, int32_t reps, const int32_t *cand,
+                    int32_t n_cand, hipStream_t stream, int32_t *best_out, float *best_ms_out) {
+    const size_t esz = direction == DD_ADJOINT ? 4 : (in_type == DD_F32 ? 4 : in_type == DD_F16 ? 2 : 1);
+    const int64_t in_rows = direction == DD_FORWARD ? p->C : p->D;
+    const int64_t in_cols = direction == DD_FORWARD ? p->T_in : p->S;
+    const int64_t out_rows = direction == DD_FORWARD ? p->D : p->C;
+    const int64_t out_cols = direction == DD_FORWARD ? p->S : p->T_in;
+    void *d_in = nullptr;
+    float *d_out = nullptr;
+    if (hipMalloc(&d_in, (size_t)in_rows * in_cols * esz) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&d_out), (size_t)out_rows * out_cols * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(d_in);
+        return fail(DD_ENOMEM, "tuning scratch allocation failed");
+    }
+    int rc = DD_OK;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int32_t best = -1;
+    float best_t = 0.f;
+    do {
+        if (hipMemsetAsync(d_in, 0, (size_t)in_rows * in_cols * esz, stream) != hipSuccess ||
+            hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            rc = fail(DD_EHIP, "tuning setup failed");
+            break;
+        }
+        const int32_t in_t = direction == DD_FORWARD ? in_type : (int32_t)DD_F32;
+        for (int32_t i = 0; i < n_cand && rc == DD_OK; ++i) {
+            const Variant *v = find_variant(cand[i]);
+            if (!v || !variant_fits(p, direction, *v))
+                continue;
+            rc = run_direction(p, direction, in_t, *v, d_in, in_cols, d_out, out_cols, stream);  // warm-up
+            if (rc != DD_OK)
+                break;
+            (void)hipEventRecord(e0, stream);
+            for (int32_t r = 0; r < reps && rc == DD_OK; ++r)
+                rc = run_direction(p, direction, in_t, *v, d_in, in_cols, d_out, out_cols, stream);
+            (void)hipEventRecord(e1, stream);
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                rc = fail(DD_EHIP, "tuning run failed");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms /= reps;
+            if (best < 0 || ms < best_t) {
+                best = v->id;
+                best_t = ms;
+            }
+        }
+    } while (false);
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(stream);
+    (void)hipFree(d_in);
+    (void)hipFree(d_out);
+    if (rc != DD_OK)
+        return rc;
+    if (best < 0)
+        return fail(DD_EUNSUPPORTED, "no tile variant can serve this plan");
+    *best_out = best;
+    *best_ms_out = best_t;
+    return DD_OK;
+}
+
+}  // namespace dd
+
+static int check_tune_args(const dd_plan *p, int direction, int in_type, int32_t reps) {
+    if (!p)
+        return fail(DD_EINVAL, "plan is NULL");
+    if (direction != DD_FORWARD && direction != DD_ADJOINT)
+        return fail(DD_EINVAL, "unknown direction %d", direction);
+    if (in_type != DD_F32 && in_type != DD_F16 && in_type != DD_U8)
+        return fail(DD_EINVAL, "unknown input dtype %d", in_type);
+    if (direction == DD_ADJOINT && in_type != DD_F32)
+        return fail(DD_EINVAL, "the adjoint works on float32 only");
+    if (reps < 1 || reps > 1000)
+        return fail(DD_EINVAL, "reps must be in [1, 1000]");
+    return DD_OK;
+}
+
+extern "C" int dd_autotune(dd_plan *p, dd_direction direction, dd_dtype in_type, int32_t reps,
+                           const char *cache_path, void *stream_v, int32_t *best_variant, float *best_ms) {
+    clear_error();
+    int rc = check_tune_args(p, direction, in_type, reps);
+    if (rc != DD_OK)
+        return rc;
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    const std::string key = cache_key(p, direction, in_type);
+    int32_t best = -1;
+    float best_t = 0.f;
+    if (!(cache_path && cache_lookup(cache_path, key, &best, &best_t) &&
+          variant_fits(p, direction, *find_variant(best)))) {
+        int32_t n = 0;
+        variants(&n);
+        std::vector<int32_t> all(n);
+        for (int32_t i = 0; i < n; ++i)
+            all[i] = i;
+        rc = tune_candidates(p, direction, in_type, reps, all.data(), n, stream, &best, &best_t);
+        if (rc != DD_OK)
+            return rc;
+        if (cache_path)
+            cache_store(cache_path, key, best, best_t);
+    }
+    {
+        std::lock_guard<std::mutex> lock(p->mu);
+        p->tuned[direction][in_type] = best;
+    }
+    if (best_variant)
+        *best_variant = best;
+    if (best_ms)
+        *best_ms = best_t;
+    return DD_OK;
+}
+
+extern "C" int dd_batch_autotune(dd_plan *const *plans, int32_t n_beams, dd_dtype in_type, int32_t reps,
+                                 const char *cache_path, void *stream_v) {
+    clear_error();
+    if (!plans || n_beams < 1)
+        return fail(DD_EINVAL, "plans is NULL or n_beams < 1");
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    for (int32_t b = 0; b < n_beams; ++b) {
+        dd_plan *p = plans[b];
+        int rc = check_tune_args(p, DD_FORWARD, in_type, reps);
+        if (rc != DD_OK)
+            return rc;
+        const std::string key = cache_key(p, DD_FORWARD, in_type) + "|batch";
+        int32_t best = -1;
+        float best_t = 0.f;
+        if (!(cache_path && cache_lookup(cache_path, key, &best, &best_t) && batch_slot_of_variant(best) >= 0 &&
+              variant_fits(p, DD_FORWARD, *find_variant(best)))) {
+            rc = tune_candidates(p, DD_FORWARD, in_type, reps, kBatchFamily, kBatchFamilySize, stream, &best, &best_t);
+            if (rc != DD_OK)
+                return rc;
+            if (cache_path)
+                cache_store(cache_path, key, best, best_t);
+        }
+        std::lock_guard<std::mutex> lock(p->mu);
+        p->tuned_batch[in_type] = best;
+    }
+    return DD_OK;
+}

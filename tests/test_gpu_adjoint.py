@@ -1,0 +1,159 @@
+"""Adjoint kernel and the autograd wrapper against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_1601_05052_amd import DD_ADJOINT, Dedisperse, Plan, dedisperse, dedisperse_adjoint, tile_variants
+from tests import gates
+from tests.gpu_util import oracle_delays, sample_points, to_dev, to_host, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+
+def test_adjoint_tiny_vs_oracle():
+    s = synth.TINY
+    plan = Plan.from_setup(s)
+    table = oracle_delays(s)
+    T = plan.input_samples
+    gy = synth.noise_f32(s.n_dm, s.n_samples, seed=21)
+    gx = to_host(dedisperse_adjoint(to_dev(gy), plan))
+    assert gx.shape == (s.n_channels, T)
+    ref = oracle.adjoint(gy, table, T)
+    absref = oracle.adjoint(np.abs(gy.astype(np.float64)), table, T)
+    gates.gate(gx, ref, absref, what="adjoint tiny")
+
+
+RAGGED = [
+    (37, 1400.0, 2.5, 5e-5, 0.0, 0.75, 77, 1001),
+    (5, 140.0, 0.2, 5e-6, 0.0, 0.02, 9, 3333),
+    (1, 1400.0, 1.0, 5e-5, 0.0, 1.0, 1, 1),
+    (130, 1420.0, 300.0 / 130, 5e-5, 10.0, 0.25, 33, 515),
+]
+
+
+@pytest.mark.parametrize("args", RAGGED, ids=lambda a: "C%d_D%d_S%d" % (a[0], a[6], a[7]))
+def test_adjoint_every_variant_integer_exact(args):
+    C, D, S = args[0], args[6], args[7]
+    plan = Plan(*args)
+    table = oracle.delay_table(*args[:7])
+    T = plan.input_samples
+    gy = synth.integers_f32(D, S + 2, seed=D)
+    ref = oracle.adjoint(gy[:, :S], table, T)
+    gyd = to_dev(gy)
+    for vid, *_ in tile_variants():
+        try:
+            plan.set_tile(vid, direction=DD_ADJOINT)
+        except Exception:
+            continue
+        gx = to_host(dedisperse_adjoint(gyd, plan))
+        gates.exact(gx, ref, what="adjoint variant %d" % vid)
+
+
+def test_adjoint_writes_zeros_and_keeps_padding():
+    torch = torch_mod()
+    s = synth.TINY
+    plan = Plan.from_setup(s)
+    T = plan.input_samples
+    gy = torch.zeros((s.n_dm, s.n_samples), device="cuda")
+    out = torch.full((s.n_channels, T + 9), float("nan"), device="cuda")
+    dedisperse_adjoint(gy, plan, out=out)
+    o = to_host(out)
+    assert np.all(o[:, :T] == 0.0)
+    assert np.all(np.isnan(o[:, T:]))
+
+
+@pytest.mark.parametrize("setup", [synth.APERTIF, synth.LOFAR], ids=lambda s: s.name)
+def test_dot_product_full_size(setup):
+    """<A x, y> = <x, A^T y> with GPU A and A^T, inner products in FP64."""
+    plan = Plan.from_setup(setup)
+    T = plan.input_samples
+    x = synth.noise_f32(setup.n_channels, T, seed=31)
+    gy = synth.noise_f32(setup.n_dm, setup.n_samples, seed=32)
+    ax = to_host(dedisperse(to_dev(x), plan)).astype(np.float64)
+    aty = to_host(dedisperse_adjoint(to_dev(gy), plan)).astype(np.float64)
+    lhs = float(np.dot(ax.ravel(), gy.astype(np.float64).ravel()))
+    rhs = float(np.dot(x.astype(np.float64).ravel(), aty.ravel()))
+    scale = float(np.dot(np.abs(ax).ravel(), np.abs(gy).astype(np.float64).ravel()))
+    assert abs(lhs - rhs) <= 1e-6 * scale, (lhs, rhs, scale)
+
+
+def test_apertif_adjoint_sampled_columns():
+    """Full-size adjoint checked on whole channel rows against the oracle."""
+    s = synth.APERTIF
+    plan = Plan.from_setup(s)
+    table = oracle_delays(s)
+    T = plan.input_samples
+    gy = synth.integers_f32(s.n_dm, s.n_samples, seed=41, lo=-3, hi=3)
+    gx = to_host(dedisperse_adjoint(to_dev(gy), plan))
+    for ch in (0, 511, 1023):
+        sub = table[:, ch:ch + 1]
+        ref = oracle.adjoint(gy, np.ascontiguousarray(sub), T)[0]
+        gates.exact(gx[ch], ref, what="adjoint ch %d" % ch)
+
+
+def _loss_grad_reference(x, w, table, S):
+    """Gradient of sum w * (A x)^2 is 2 A^T (w * A x), all in FP64."""
+    y = oracle.dedisperse(x, table, S)
+    return y, oracle.adjoint(2.0 * w * y, table, x.shape[1])
+
+
+def test_autograd_fd_slice():
+    """16-ch x 32-DM x 256-sample slice: the autograd gradient matches the
+    FP64 gradient, and central finite differences of the FP64 loss (exact for
+    this quadratic loss with integer x, dyadic w, h = 1) match it too."""
+    torch = torch_mod()
+    s = synth.FD_SLICE
+    plan = Plan.from_setup(s)
+    table = oracle_delays(s)
+    T = plan.input_samples
+    x = synth.integers_f32(s.n_channels, T, seed=51, lo=-4, hi=4)
+    w = (np.random.default_rng(52).integers(0, 16, size=(s.n_dm, s.n_samples)) / 16.0).astype(np.float32)
+    xt = to_dev(x).requires_grad_(True)
+    wt = to_dev(w)
+    out = Dedisperse.apply(xt, plan)
+    loss = (wt * out * out).sum()
+    loss.backward()
+    g = to_host(xt.grad)
+    _, gref = _loss_grad_reference(x.astype(np.float64), w.astype(np.float64), table, s.n_samples)
+    gates.exact(g, gref, what="autograd gradient")
+
+    def loss64(xx):
+        y = oracle.dedisperse(xx, table, s.n_samples)
+        return float(np.sum(w.astype(np.float64) * y * y))
+
+    rng = np.random.default_rng(53)
+    x64 = x.astype(np.float64)
+    for _ in range(24):
+        ch, tau = int(rng.integers(0, s.n_channels)), int(rng.integers(0, T))
+        xp, xm = x64.copy(), x64.copy()
+        xp[ch, tau] += 1.0
+        xm[ch, tau] -= 1.0
+        fd = (loss64(xp) - loss64(xm)) / 2.0
+        assert fd == gref[ch, tau] == g[ch, tau], (ch, tau, fd, gref[ch, tau], g[ch, tau])
+
+
+def test_autograd_apertif_beam_vs_oracle_sampled():
+    """One Apertif-shaped beam of the fwd+bwd workload: the gradient of
+    sum w * out^2 against the FP64 chain 2 A^T (w * A x) on whole channel
+    rows.  The componentwise bound uses the magnitude of every term the GPU
+    rounds: |2 w| * (|A x| + A|x|) pushed through A^T."""
+    s = synth.fwd_bwd_beams(1)[0]
+    plan = Plan.from_setup(s)
+    table = oracle_delays(s)
+    T = plan.input_samples
+    x = synth.noise_f32(s.n_channels, T, seed=s.seed)
+    w = synth.uniform_f32(s.n_dm, s.n_samples, seed=s.seed + 1000)
+    xt = to_dev(x).requires_grad_(True)
+    out = Dedisperse.apply(xt, plan)
+    (to_dev(w) * out * out).sum().backward()
+    g = to_host(xt.grad)
+    chans = [0, 700, 1023]
+    sub = np.ascontiguousarray(table[:, chans])
+    w64 = w.astype(np.float64)
+    yref = oracle.dedisperse(x, table, s.n_samples)
+    yabs = oracle.dedisperse(np.abs(x.astype(np.float64)), table, s.n_samples)
+    gref = oracle.adjoint(2.0 * w64 * yref, sub, T)
+    bound = oracle.adjoint(2.0 * w64 * (np.abs(yref) + yabs), sub, T)
+    for k, ch in enumerate(chans):
+        gates.gate(g[ch], gref[k], bound[k], what="grad ch %d" % ch)

@@ -1,0 +1,92 @@
+"""Batched persistent launch: every beam equals the oracle and its own
+single-beam run; graph replays pick up new inputs and pointers."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_1601_05052_amd import DD_F16, DD_F32, DD_U8, Batch, Plan, dedisperse
+from tests import gates
+from tests.gpu_util import sample_points, to_dev, to_host, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+
+def small_beams():
+    """Uneven beams small enough for full oracle checks."""
+    out = []
+    rng = np.random.default_rng(99)
+    for b in range(7):
+        c = int(rng.choice([16, 32, 64, 100]))
+        d = int(rng.integers(20, 200))
+        s = int(rng.integers(300, 3000))
+        out.append(synth.Setup("sb%d" % b, c, 1420.0, 300.0 / c, 1.0 / 20000, 0.0, 0.25 * (b + 1), d, s,
+                               seed=900 + b))
+    return out
+
+
+@pytest.mark.parametrize("dtype,code", [("f32", DD_F32), ("u8", DD_U8), ("f16", DD_F16)])
+def test_batch_matches_oracle_and_single_beam(dtype, code):
+    beams = small_beams()
+    plans = [Plan.from_setup(b) for b in beams]
+    xs_h = []
+    for b, p in zip(beams, plans):
+        x = {"f32": synth.noise_f32, "u8": synth.noise_u8, "f16": synth.noise_f16}[dtype](
+            b.n_channels, p.input_samples + 3, b.seed)
+        xs_h.append(x)
+    xs = [to_dev(x) for x in xs_h]
+    batch = Batch(plans, dtype=code)
+    outs = batch.run(xs)
+    for b, p, x, y in zip(beams, plans, xs_h, outs):
+        table = oracle.delay_table(*b.plan_args()[:7])
+        yh = to_host(y)
+        ref = oracle.dedisperse(x, table, b.n_samples)
+        if dtype == "u8":
+            gates.exact(yh, ref, what=b.name)
+        else:
+            absref = oracle.dedisperse(np.abs(x.astype(np.float64)), table, b.n_samples)
+            gates.gate(yh, ref, absref, what=b.name)
+        single = to_host(dedisperse(to_dev(x), p))
+        if p.get_tile(dtype=code) in batch_family():
+            assert np.array_equal(single, yh), b.name
+
+
+def batch_family():
+    return {0, 1, 2, 3, 6, 7, 8}
+
+
+def test_batch_replay_new_data_and_pointers():
+    torch = torch_mod()
+    beams = small_beams()[:4]
+    plans = [Plan.from_setup(b) for b in beams]
+    batch = Batch(plans)
+    for rep in range(3):
+        xs_h = [synth.integers_f32(b.n_channels, p.input_samples, seed=rep * 10 + i)
+                for i, (b, p) in enumerate(zip(beams, plans))]
+        xs = [to_dev(x) for x in xs_h]
+        outs = [torch.full((p.n_dm, p.n_samples + 4), float("nan"), device="cuda") for p in plans]
+        batch.run(xs, outs)
+        torch.cuda.synchronize()
+        for b, x, o in zip(beams, xs_h, outs):
+            oh = to_host(o)
+            table = oracle.delay_table(*b.plan_args()[:7])
+            gates.exact(oh[:, :b.n_samples], oracle.dedisperse(x, table, b.n_samples), what="rep%d" % rep)
+            assert np.all(np.isnan(oh[:, b.n_samples:]))
+
+
+def test_batched_workload_sampled_u8():
+    """The 64-beam Apertif-band batch (u8 storage) in one launch: every beam's
+    sampled outputs are bit-exact against the oracle."""
+    torch = torch_mod()
+    beams = synth.batched_beams()
+    plans = [Plan.from_setup(b) for b in beams]
+    xs_h = [synth.noise_u8(b.n_channels, p.input_samples, b.seed) for b, p in zip(beams, plans)]
+    xs = [to_dev(x) for x in xs_h]
+    batch = Batch(plans, dtype=DD_U8)
+    outs = batch.run(xs)
+    torch.cuda.synchronize()
+    for b, x, y in zip(beams, xs_h, outs):
+        table = oracle.delay_table(*b.plan_args()[:7])
+        i, t = sample_points(b.n_dm, b.n_samples, 400, b.seed)
+        yh = y[torch.from_numpy(i).long().cuda(), torch.from_numpy(t).long().cuda()].cpu().numpy()
+        gates.exact(yh, oracle.dedisperse_points(x, table, i, t), what=b.name)

@@ -1,0 +1,174 @@
+"""libdedisp on the CPU: it loads, exports what include/dedisp.h declares,
+builds delay tables bit-identical to the oracle's, and rejects bad arguments
+before touching any GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_1601_05052_amd import _lib
+from paper_1601_05052_amd import Plan, DedispError, tile_variants
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dedisp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dd_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_api():
+    names = declared_functions()
+    for must in ("dd_plan_create", "dd_dedisperse", "dd_dedisperse_adjoint", "dd_autotune",
+                 "dd_batch_create", "dd_batch_run", "dd_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(_lib.SIGNATURES), "binding and header disagree"
+
+
+def test_version_string():
+    assert b"gfx950" in _lib.lib().dd_version()
+
+
+@pytest.mark.parametrize("setup", [synth.TINY, synth.APERTIF, synth.LOFAR, synth.FD_SLICE],
+                         ids=lambda s: s.name)
+def test_delay_table_bit_exact_vs_oracle(setup):
+    p = Plan.from_setup(setup)
+    mine = p.delays()
+    ref = oracle.delay_table(*setup.plan_args()[:7])
+    assert mine.dtype == np.int32 and mine.shape == ref.shape
+    assert np.array_equal(mine, ref)
+    assert p.max_delay == int(ref.max())
+    assert p.input_samples == setup.n_samples + int(ref.max())
+
+
+def test_delay_table_bit_exact_batched_and_random():
+    for beam in synth.batched_beams():
+        p = Plan.from_setup(beam)
+        assert np.array_equal(p.delays(), oracle.delay_table(*beam.plan_args()[:7])), beam.name
+    rng = np.random.default_rng(123)
+    for _ in range(40):
+        C = int(rng.integers(1, 300))
+        f_min = float(rng.uniform(50, 2000))
+        df = float(rng.uniform(0.001, 5.0))
+        t_samp = float(rng.uniform(1e-6, 1e-3))
+        dm_first = float(rng.uniform(0, 100))
+        dm_step = float(rng.uniform(0, 3))
+        D = int(rng.integers(1, 200))
+        args = (C, f_min, df, t_samp, dm_first, dm_step, D)
+        p = Plan(*args, 1000)
+        assert np.array_equal(p.delays(), oracle.delay_table(*args)), args
+
+
+def test_plan_dims():
+    p = Plan.from_setup(synth.TINY)
+    c, d, s = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    _lib.check(_lib.lib().dd_plan_dims(p.handle, ctypes.byref(c), ctypes.byref(d), ctypes.byref(s)))
+    assert (c.value, d.value, s.value) == (64, 128, 4096)
+
+
+BAD_PLANS = [
+    dict(n_channels=0), dict(n_dm=0), dict(n_samples=0), dict(f_min=0.0), dict(f_min=-5.0),
+    dict(df=0.0), dict(df=-1.0), dict(t_samp=0.0), dict(dm_first=-1.0), dict(dm_step=-0.25),
+    dict(f_min=float("nan")), dict(df=float("inf")), dict(t_samp=float("nan")),
+    dict(dm_step=float("inf")),
+    dict(f_min=10.0, t_samp=1e-12, dm_step=1e6),   # delays beyond int32
+]
+
+
+@pytest.mark.parametrize("bad", BAD_PLANS, ids=lambda b: ",".join("%s=%s" % kv for kv in b.items()))
+def test_plan_rejects_invalid(bad):
+    args = dict(n_channels=8, f_min=1400.0, df=1.0, t_samp=5e-5, dm_first=0.0, dm_step=0.5, n_dm=4,
+                n_samples=64)
+    args.update(bad)
+    with pytest.raises(DedispError) as e:
+        Plan(**args)
+    assert e.value.code == _lib.DD_EINVAL
+    assert _lib.lib().dd_last_error()
+
+
+def _fake(addr):
+    return ctypes.c_void_p(addr)
+
+
+def test_compute_calls_reject_bad_arguments_before_gpu_work():
+    """Shape / stride / pointer errors return before any HIP call, so they can
+    be exercised without a GPU using fake (never dereferenced) pointers."""
+    L = _lib.lib()
+    p = Plan.from_setup(synth.TINY)
+    h, T, S = p.handle, p.input_samples, p.n_samples
+    IN, OUT = 0x100000, 0x90000000
+    cases = [
+        (L.dd_dedisperse(None, _fake(IN), 0, T, _fake(OUT), S, None), _lib.DD_EINVAL),
+        (L.dd_dedisperse(h, None, 0, T, _fake(OUT), S, None), _lib.DD_EINVAL),
+        (L.dd_dedisperse(h, _fake(IN), 0, T, None, S, None), _lib.DD_EINVAL),
+        (L.dd_dedisperse(h, _fake(IN), 7, T, _fake(OUT), S, None), _lib.DD_EINVAL),
+        (L.dd_dedisperse(h, _fake(IN), 0, T - 1, _fake(OUT), S, None), _lib.DD_ESHAPE),
+        (L.dd_dedisperse(h, _fake(IN), 0, T, _fake(OUT), S - 1, None), _lib.DD_ESHAPE),
+        (L.dd_dedisperse(h, _fake(IN + 2), 0, T, _fake(OUT), S, None), _lib.DD_ESHAPE),
+        (L.dd_dedisperse(h, _fake(IN), 0, T, _fake(IN + 64), S, None), _lib.DD_ESHAPE),  # overlap
+        (L.dd_dedisperse_adjoint(h, _fake(OUT), S - 1, _fake(IN), T, None), _lib.DD_ESHAPE),
+        (L.dd_dedisperse_adjoint(h, _fake(OUT), S, _fake(IN), T - 1, None), _lib.DD_ESHAPE),
+        (L.dd_dedisperse_adjoint(h, _fake(OUT), S, _fake(OUT + 4), T, None), _lib.DD_ESHAPE),
+        (L.dd_dedisperse_adjoint(h, None, S, _fake(IN), T, None), _lib.DD_EINVAL),
+        (L.dd_plan_set_tile(h, 0, 0, 999), _lib.DD_EINVAL),
+        (L.dd_plan_set_tile(h, 5, 0, 0), _lib.DD_EINVAL),
+        (L.dd_autotune(h, 1, 2, 3, None, None, None, None), _lib.DD_EINVAL),
+        (L.dd_autotune(h, 0, 0, 0, None, None, None, None), _lib.DD_EINVAL),
+    ]
+    for got, want in cases:
+        assert got == want
+        assert L.dd_last_error()
+
+
+def test_null_plan_queries():
+    L = _lib.lib()
+    v = ctypes.c_int32()
+    assert L.dd_plan_max_delay(None, ctypes.byref(v)) == _lib.DD_EINVAL
+    assert L.dd_plan_destroy(None) == _lib.DD_OK
+    assert L.dd_batch_destroy(None) == _lib.DD_OK
+    assert L.dd_batch_create(None, None, 0, 0) == _lib.DD_EINVAL
+
+
+def test_tile_variants_cover_paper_parameters():
+    """Sec. III-B: work-items and elements per work-item, in time and in DM."""
+    vs = tile_variants()
+    assert len(vs) >= 8
+    for i, (vid, it, ia, waves, kind) in enumerate(vs):
+        assert vid == i
+        assert it >= 1 and ia >= 1 and 1 <= waves <= 16 and kind in (0, 1)
+    assert {v[4] for v in vs} == {0, 1}, "both the LDS and the register-window kernels are compiled"
+
+
+def test_set_tile_rejects_window_too_large():
+    """A 64-row DM tile on the LOFAR-like setup needs a staging window wider
+    than LDS; the 1-row variant always fits."""
+    p = Plan.from_setup(synth.LOFAR)
+    wide = [v[0] for v in tile_variants() if v[2] * v[3] == 64]
+    with pytest.raises(DedispError):
+        p.set_tile(wide[0], direction=_lib.DD_ADJOINT)
+    one = [v[0] for v in tile_variants() if v[2] * v[3] == 1][0]
+    p.set_tile(one, direction=_lib.DD_ADJOINT)
+    assert p.get_tile(direction=_lib.DD_ADJOINT) == one
+    p.set_tile(-1, direction=_lib.DD_ADJOINT)
+
+
+def test_fault_injection_alloc(monkeypatch):
+    """DD_FAULT_INJECT=alloc makes table allocation fail with DD_ENOMEM (the
+    failure happens before any device call)."""
+    monkeypatch.setenv("DD_FAULT_INJECT", "alloc")
+    p = Plan.from_setup(synth.TINY)
+    rc = _lib.lib().dd_plan_prepare(p.handle, 0, 0)
+    # Without a GPU, hipGetDevice may fail first (DD_EHIP); with one, DD_ENOMEM.
+    assert rc in (_lib.DD_ENOMEM, _lib.DD_EHIP)
