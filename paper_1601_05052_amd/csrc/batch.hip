@@ -99,13 +99,13 @@ __global__ void __launch_bounds__(256)
         // Slot -> tile routine; must match kBatchFamily.
         switch (bd.slot) {
         case 0:
-            dev::srs_tile_regwin<TIn, 8, 8, 4, 1, 12>(in, bp.out, bd.base, bd.wrec, bd.woff, d, tile_t, tile_a, lds);
+            dev::srs_tile_regwin<TIn, 8, 8, 4, 1, 12, false>(in, bp.out, bd.base, bd.wrec, bd.woff, d, tile_t, tile_a, lds);
             break;
         case 1:
-            dev::srs_tile_regwin<TIn, 8, 4, 4, 2, 16>(in, bp.out, bd.base, bd.wrec, bd.woff, d, tile_t, tile_a, lds);
+            dev::srs_tile_regwin<TIn, 8, 4, 4, 2, 16, false>(in, bp.out, bd.base, bd.wrec, bd.woff, d, tile_t, tile_a, lds);
             break;
         case 2:
-            dev::srs_tile_regwin<TIn, 4, 8, 4, 2, 12>(in, bp.out, bd.base, bd.wrec, bd.woff, d, tile_t, tile_a, lds);
+            dev::srs_tile_regwin<TIn, 4, 8, 4, 2, 12, false>(in, bp.out, bd.base, bd.wrec, bd.woff, d, tile_t, tile_a, lds);
             break;
         case 3: dev::srs_tile_lds<TIn, 4, 8, 4>(in, bp.out, bd.rel, bd.base, d, tile_t, tile_a, lds); break;
         case 4: dev::srs_tile_lds<TIn, 4, 4, 4>(in, bp.out, bd.rel, bd.base, d, tile_t, tile_a, lds); break;

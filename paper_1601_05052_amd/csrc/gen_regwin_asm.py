@@ -155,6 +155,18 @@ def gen_config(it, tdw, nwr, acc0):
     L.append("            : " + ", ".join(['[addr] "v"(addr)', '[nq] "s"(nq)'] + o_ins))
     L.extend(clobbers(wa))
     L.append("    }")
+    # Same, loading the whole window (no branches).
+    L.append("    __device__ static __forceinline__ void row_full(Acc &a, uint32_t addr, const int (&o)[%d]) {" % tdw)
+    L.append("        asm volatile(")
+    for q in range(nq_max):
+        L.append('            "ds_read_b128 v[%d:%d], %%[addr] offset:%d\\n\\t"'
+                 % (w0 + 4 * q, w0 + 4 * q + 3, 16 * quad_offset(q, s)))
+    L.append('            "s_waitcnt lgkmcnt(0)\\n\\t"')
+    L.extend(adds(w0))
+    L.append("            : " + ", ".join(outs))
+    L.append("            : " + ", ".join(['[addr] "v"(addr)'] + o_ins))
+    L.extend(clobbers(wa))
+    L.append("    }")
     L.append("};")
     return "\n".join(L)
 

@@ -131,7 +131,16 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
     if (!ok)
         return;
     const int64_t lds_limit = 160 * 1024;
-    if (v.kind == KIND_LDS) {
+    if (v.kind == KIND_LDS && v.kmax > 0) {
+        // Prefetched staging: rows padded to whole 64-sample pieces, two buffers.
+        const int64_t w64 = ((int64_t)TT + max_spread + 63) & ~int64_t(63);
+        const int64_t rows = (int64_t)v.waves * v.rpw;
+        if (w64 > (int64_t)64 * v.kmax || 2 * rows * w64 * 4 > lds_limit)
+            return;
+        L->wcap = (int32_t)w64;
+        L->rows_per_chunk = (int32_t)rows;
+        L->lds_bytes = (int32_t)(2 * rows * w64 * 4);
+    } else if (v.kind == KIND_LDS) {
         const int64_t w4 = ((int64_t)TT + max_spread + 3) & ~int64_t(3);
         const int64_t row_bytes = w4 * 4;
         if (row_bytes > lds_limit)
@@ -148,11 +157,11 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
         const int64_t rows = (int64_t)v.waves * v.rpw;
         const int64_t S = v.items_t / 4;
         const int64_t row_dw = S == 1 ? w64 : w64 / S * (S + 1);  // padded layout
-        if (rows * row_dw * 4 > lds_limit || (need >> 20) != 0)
+        if (2 * rows * row_dw * 4 > lds_limit || (need >> 20) != 0)   // two chunk buffers
             return;
         L->wcap = (int32_t)w64;
         L->rows_per_chunk = (int32_t)rows;
-        L->lds_bytes = (int32_t)(rows * row_dw * 4);
+        L->lds_bytes = (int32_t)(2 * rows * row_dw * 4);
     }
     L->feasible = true;
 }

@@ -14,8 +14,9 @@
 //
 // Staging: every wave owns RPW rows of each chunk of NW*RPW input rows.  Its
 // lanes fetch them with bounds-checked buffer loads (samples outside
-// [0, in_valid) read as zero), one chunk ahead, into registers; after the
-// chunk is consumed they are written to LDS.
+// [0, in_valid) read as zero) into registers two chunks ahead and write them
+// to the other of two LDS chunk buffers; one barrier per chunk.  FULL loads the
+// whole register window for every row instead of only the quads it needs.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -82,7 +83,7 @@ __device__ __forceinline__ uint32_t lds_address(const float *p) {
     return static_cast<uint32_t>(reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) float *)p));
 }
 
-template <typename TIn, int IT, int TDW, int NW, int RPW, int KMAX>
+template <typename TIn, int IT, int TDW, int NW, int RPW, int KMAX, bool FULL>
 __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, float *__restrict__ out,
                                                 const int32_t *__restrict__ base,
                                                 const int32_t *__restrict__ wrec,
@@ -105,47 +106,46 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
     for (int i = 0; i < IT * TDW; ++i)
         RW::set_acc(acc, i, 0.f);
 
-    float pre[RPW][KMAX];
-    const int32_t n_chunks = (d.n_rows + CR - 1) / CR;
-#pragma unroll
-    for (int q = 0; q < RPW; ++q) {
-        const int32_t row = wave * RPW + q;
-        if (row < d.n_rows)
-            fetch_row<TIn, KMAX>(in, d.in_stride, d.in_valid, row, t0 + base_tile[row], nk, lane, pre[q]);
-    }
-
     // Padded LDS row layout (see regwin_asm.h): logical quad Q at physical
-    // quad Q + floor(Q/S) (no padding when S == 1).
+    // quad Q + floor(Q/S) (no padding when S == 1).  Two chunk buffers.
     constexpr int S = RW::S;
     const int32_t row_dw = S == 1 ? d.wcap : d.wcap / S * (S + 1);  // physical dwords per row
     const int32_t lane_st = S == 1 ? lane : 4 * ((lane >> 2) + ((lane >> 2) / S)) + (lane & 3);
     constexpr int32_t piece_dw = S == 1 ? 64 : 64 / S * (S + 1);       // physical dwords per 64 samples
-    const uint32_t lds_base = lds_address(lds);
-    const uint32_t lane_rd = lds_base + static_cast<uint32_t>(lane) * 16u * (S == 1 ? 1u : S + 1u);
+    const int32_t buf_dw = CR * row_dw;
+    const uint32_t lane_rd = lds_address(lds) + static_cast<uint32_t>(lane) * 16u * (S == 1 ? 1u : S + 1u);
 
-    for (int32_t c = 0; c < n_chunks; ++c) {
-        const int32_t r0 = c * CR;
-        __syncthreads();  // every wave has finished reading the previous chunk
+    float pre[RPW][KMAX];
+    const int32_t n_chunks = (d.n_rows + CR - 1) / CR;
+    auto fetch_chunk = [&](int32_t c) {
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+            const int32_t row = c * CR + wave * RPW + q;
+            if (row < d.n_rows)
+                fetch_row<TIn, KMAX>(in, d.in_stride, d.in_valid, row, t0 + base_tile[row], nk, lane, pre[q]);
+        }
+    };
+    auto store_chunk = [&](int32_t c) {
 #pragma unroll
         for (int q = 0; q < RPW; ++q) {
             const int32_t rr = wave * RPW + q;
-            if (r0 + rr < d.n_rows) {
-                float *dst = lds + rr * row_dw + lane_st;
+            if (c * CR + rr < d.n_rows) {
+                float *dst = lds + (c & 1) * buf_dw + rr * row_dw + lane_st;
 #pragma unroll
                 for (int k = 0; k < KMAX; ++k)
                     if (k < nk)
                         dst[piece_dw * k] = pre[q][k];
             }
         }
-        __syncthreads();  // chunk c is staged
-        if (c + 1 < n_chunks) {
-#pragma unroll
-            for (int q = 0; q < RPW; ++q) {
-                const int32_t row = r0 + CR + wave * RPW + q;
-                if (row < d.n_rows)
-                    fetch_row<TIn, KMAX>(in, d.in_stride, d.in_valid, row, t0 + base_tile[row], nk, lane, pre[q]);
-            }
-        }
+    };
+
+    fetch_chunk(0);
+    store_chunk(0);
+    if (n_chunks > 1)
+        fetch_chunk(1);
+    __syncthreads();  // chunk 0 staged
+    for (int32_t c = 0; c < n_chunks; ++c) {
+        const int32_t r0 = c * CR;
         const int32_t nr = min(CR, d.n_rows - r0);
         // Window records and offsets of this wave's accumulator rows for the chunk.
         int rec[CR];
@@ -160,14 +160,25 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
             for (int a = 0; a < TDW; ++a)
                 o[rr][a] = __builtin_amdgcn_readfirstlane(woff_tile[static_cast<int64_t>(r) * NW * TDW + a]);
         }
-        auto addr_of = [&](int rr) {
-            return lane_rd + static_cast<uint32_t>(rr * row_dw) * 4u + static_cast<uint32_t>(rec[rr] & 0xfffff);
-        };
+        const uint32_t chunk_rd = lane_rd + static_cast<uint32_t>((c & 1) * buf_dw) * 4u;
 #pragma unroll
         for (int rr = 0; rr < CR; ++rr) {
             if (rr >= nr)
                 break;
-            RW::row(acc, addr_of(rr), rec[rr] >> 20, o[rr]);
+            const uint32_t addr =
+                chunk_rd + static_cast<uint32_t>(rr * row_dw) * 4u + static_cast<uint32_t>(rec[rr] & 0xfffff);
+            if constexpr (FULL)
+                RW::row_full(acc, addr, o[rr]);
+            else
+                RW::row(acc, addr, rec[rr] >> 20, o[rr]);
+        }
+        if (c + 1 < n_chunks) {
+            // The other buffer was last read in chunk c-1, which every wave
+            // finished before the previous barrier.
+            store_chunk(c + 1);
+            if (c + 2 < n_chunks)
+                fetch_chunk(c + 2);
+            __syncthreads();  // chunk c+1 staged; chunk c consumed by every wave
         }
     }
 
@@ -194,6 +205,101 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
             for (int j = 0; j < IT; ++j)
                 if (tl + j < d.n_t)
                     dst[j] = RW::get_acc(acc, a * IT + j);
+        }
+    }
+}
+
+// LDS form with prefetch: the staging of srs_tile_regwin (bounds-checked
+// buffer loads two chunks ahead into registers, two LDS chunk buffers, one
+// barrier per chunk; unpadded rows of wcap samples) and the addition of
+// srs_tile_lds (lane l owns samples t0 + l + 64j; every addition reads its
+// operand from LDS at a wave-uniform offset, 64 consecutive words per read).
+template <typename TIn, int IT, int TDW, int NW, int RPW, int KMAX>
+__device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float *__restrict__ out,
+                                              const int32_t *__restrict__ rel,
+                                              const int32_t *__restrict__ base, const SrsDims &d,
+                                              int32_t tile_t, int32_t tile_a, float *lds) {
+    constexpr int TT = 64 * IT;
+    constexpr int TA = TDW * NW;
+    constexpr int CR = NW * RPW;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t t0 = static_cast<int64_t>(tile_t) * TT;
+    const int32_t *base_tile = base + static_cast<int64_t>(tile_a) * d.n_rows;
+    const int32_t *rel_tile = rel + static_cast<int64_t>(tile_a) * d.n_rows * TA + wave * TDW;
+    const int32_t nk = d.wcap >> 6;
+    const int32_t buf_dw = CR * d.wcap;
+
+    float acc[TDW][IT];
+#pragma unroll
+    for (int k = 0; k < TDW; ++k)
+#pragma unroll
+        for (int j = 0; j < IT; ++j)
+            acc[k][j] = 0.f;
+
+    float pre[RPW][KMAX];
+    const int32_t n_chunks = (d.n_rows + CR - 1) / CR;
+    auto fetch_chunk = [&](int32_t c) {
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+            const int32_t row = c * CR + wave * RPW + q;
+            if (row < d.n_rows)
+                fetch_row<TIn, KMAX>(in, d.in_stride, d.in_valid, row, t0 + base_tile[row], nk, lane, pre[q]);
+        }
+    };
+    auto store_chunk = [&](int32_t c) {
+#pragma unroll
+        for (int q = 0; q < RPW; ++q) {
+            const int32_t rr = wave * RPW + q;
+            if (c * CR + rr < d.n_rows) {
+                float *dst = lds + (c & 1) * buf_dw + rr * d.wcap + lane;
+#pragma unroll
+                for (int k = 0; k < KMAX; ++k)
+                    if (k < nk)
+                        dst[64 * k] = pre[q][k];
+            }
+        }
+    };
+
+    fetch_chunk(0);
+    store_chunk(0);
+    if (n_chunks > 1)
+        fetch_chunk(1);
+    __syncthreads();
+    for (int32_t c = 0; c < n_chunks; ++c) {
+        const int32_t r0 = c * CR;
+        const int32_t nr = min(CR, d.n_rows - r0);
+        const float *buf = lds + (c & 1) * buf_dw + lane;
+        for (int32_t rr = 0; rr < nr; ++rr) {
+            const int32_t *o = rel_tile + static_cast<int64_t>(r0 + rr) * TA;
+            const float *row = buf + rr * d.wcap;
+#pragma unroll
+            for (int k = 0; k < TDW; ++k) {
+                const float *p = row + __builtin_amdgcn_readfirstlane(o[k]);
+#pragma unroll
+                for (int j = 0; j < IT; ++j)
+                    acc[k][j] += p[64 * j];
+            }
+        }
+        if (c + 1 < n_chunks) {
+            store_chunk(c + 1);
+            if (c + 2 < n_chunks)
+                fetch_chunk(c + 2);
+            __syncthreads();
+        }
+    }
+
+#pragma unroll
+    for (int k = 0; k < TDW; ++k) {
+        const int32_t ag = tile_a * TA + wave * TDW + k;
+        if (ag < d.n_acc) {
+            float *dst = out + static_cast<int64_t>(ag) * d.out_stride;
+#pragma unroll
+            for (int j = 0; j < IT; ++j) {
+                const int64_t t = t0 + lane + 64 * j;
+                if (t < d.n_t)
+                    __builtin_nontemporal_store(acc[k][j], dst + t);
+            }
         }
     }
 }
