@@ -221,6 +221,8 @@ def main():
     ap.add_argument("--workload", default="apertif", choices=["apertif", "lofar"])
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: dedispersion beams are independent and this build runs on a "
@@ -275,6 +277,13 @@ def main():
         "paper_context": {"hd7970_2000dms_s": 0.106, "hd7970_GFLOPs": round(2000 * 1024 * 20000 / 0.106 / 1e9, 1),
                           "note": "AMD HD7970, OpenCL, 2,000 DMs x 1 s Apertif (Sec. V-D); other hardware"},
     }
+    if args.calibrate_copy:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").normal_()
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_extra:
         line["extras"] = extras(torch, dd, stream, max(5, args.steps // 5))
     if not args.no_cpu_baseline:

@@ -53,7 +53,7 @@ namespace dd {
 // The batch kernel's tile family: 4-wave variants whose register footprints
 // are close, so one kernel serves them all at the occupancy of the largest.
 // Index = slot, value = variant id (see srs_kernels.hip).
-const int32_t kBatchFamily[] = {17, 12, 14, 0, 1, 3, 6, 7, 8};
+const int32_t kBatchFamily[] = {17, 19, 14, 21, 20, 24, 25, 7};
 const int32_t kBatchFamilySize = sizeof(kBatchFamily) / sizeof(kBatchFamily[0]);
 
 int32_t batch_slot_of_variant(int32_t v) {
@@ -99,20 +99,24 @@ __global__ void __launch_bounds__(256)
         // Slot -> tile routine; must match kBatchFamily.
         switch (bd.slot) {
         case 0:
-            dev::srs_tile_regwin<TIn, 8, 8, 4, 1, 12, false>(in, bp.out, bd.base, bd.wrec, bd.woff, d, tile_t, tile_a, lds);
+            dev::srs_tile_regwin<TIn, 8, 8, 40, 4, 1, 12, false>(in, bp.out, bd.base, bd.wrec, bd.woff, d, tile_t,
+                                                               tile_a, lds);
             break;
         case 1:
-            dev::srs_tile_regwin<TIn, 8, 4, 4, 2, 16, false>(in, bp.out, bd.base, bd.wrec, bd.woff, d, tile_t, tile_a, lds);
+            dev::srs_tile_regwin<TIn, 8, 4, 32, 4, 1, 12, false>(in, bp.out, bd.base, bd.wrec, bd.woff, d, tile_t,
+                                                               tile_a, lds);
             break;
         case 2:
-            dev::srs_tile_regwin<TIn, 4, 8, 4, 2, 12, false>(in, bp.out, bd.base, bd.wrec, bd.woff, d, tile_t, tile_a, lds);
+            dev::srs_tile_regwin<TIn, 4, 8, 32, 4, 2, 12, false>(in, bp.out, bd.base, bd.wrec, bd.woff, d, tile_t,
+                                                               tile_a, lds);
             break;
-        case 3: dev::srs_tile_lds<TIn, 4, 8, 4>(in, bp.out, bd.rel, bd.base, d, tile_t, tile_a, lds); break;
-        case 4: dev::srs_tile_lds<TIn, 4, 4, 4>(in, bp.out, bd.rel, bd.base, d, tile_t, tile_a, lds); break;
-        case 5: dev::srs_tile_lds<TIn, 8, 4, 4>(in, bp.out, bd.rel, bd.base, d, tile_t, tile_a, lds); break;
-        case 6: dev::srs_tile_lds<TIn, 4, 2, 4>(in, bp.out, bd.rel, bd.base, d, tile_t, tile_a, lds); break;
-        case 7: dev::srs_tile_lds<TIn, 4, 1, 4>(in, bp.out, bd.rel, bd.base, d, tile_t, tile_a, lds); break;
-        default: dev::srs_tile_lds<TIn, 2, 1, 4>(in, bp.out, bd.rel, bd.base, d, tile_t, tile_a, lds); break;
+        case 3: dev::srs_tile_ldsp<TIn, 4, 4, 4, 1, 16>(in, bp.out, bd.rel, bd.base, d, tile_t, tile_a, lds); break;
+        case 4: dev::srs_tile_ldsp<TIn, 4, 8, 4, 1, 24>(in, bp.out, bd.rel, bd.base, d, tile_t, tile_a, lds); break;
+        case 5: dev::srs_tile_ldsp<TIn, 4, 2, 4, 2, 12>(in, bp.out, bd.rel, bd.base, d, tile_t, tile_a, lds); break;
+        case 6: dev::srs_tile_ldsp<TIn, 4, 1, 4, 2, 8>(in, bp.out, bd.rel, bd.base, d, tile_t, tile_a, lds); break;
+        default:  // direct staging: fits spreads up to the LDS size
+            dev::srs_tile_lds<TIn, 4, 1, 4>(in, bp.out, bd.rel, bd.base, d, tile_t, tile_a, lds);
+            break;
         }
     }
 }

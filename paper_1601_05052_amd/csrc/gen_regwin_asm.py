@@ -42,6 +42,8 @@ CONFIGS = [
     (16, 4, 48, 24),
     (4, 8, 32, 24),
     (8, 16, 48, 24),
+    (8, 4, 44, 24),   # wider windows for the adjoint (delays spread more across channels)
+    (8, 8, 76, 24),
 ]
 
 # Register-tuple widths LLVM's AMDGPU backend can bind to one constraint.
@@ -72,7 +74,7 @@ def gen_config(it, tdw, nwr, acc0):
     w0 = acc0 + n_acc
     nq_max = nwr // 4
     acc_parts = split(n_acc)
-    name = "RegWin<%d, %d>" % (it, tdw)
+    name = "RegWin<%d, %d, %d>" % (it, tdw, nwr)
     L = []
     L.append("template <>")
     L.append("struct %s {" % name)
@@ -171,8 +173,8 @@ def gen_config(it, tdw, nwr, acc0):
     return "\n".join(L)
 
 
-def main():
-    here = os.path.dirname(os.path.abspath(__file__))
+def render() -> str:
+    """The full text of regwin_asm.h."""
     out = [
         "// GENERATED by gen_regwin_asm.py -- do not edit by hand.",
         "// Inline-assembly row step of the register-window kernel (gfx950).",
@@ -187,14 +189,18 @@ def main():
     ]
     for n in sorted({t for t in TUPLES if t > 2}):
         out.append("typedef float v%df __attribute__((ext_vector_type(%d)));" % (n, n))
-    out += ["", "template <int IT, int TDW>", "struct RegWin;", ""]
+    out += ["", "template <int IT, int TDW, int NWR>", "struct RegWin;", ""]
     for cfg in CONFIGS:
         out.append(gen_config(*cfg))
         out.append("")
     out += ["}  // namespace dev", "}  // namespace dd", ""]
-    path = os.path.join(here, "regwin_asm.h")
+    return "\n".join(out)
+
+
+def main(path=None):
+    path = path or os.path.join(os.path.dirname(os.path.abspath(__file__)), "regwin_asm.h")
     with open(path, "w") as f:
-        f.write("\n".join(out))
+        f.write(render())
     return path
 
 

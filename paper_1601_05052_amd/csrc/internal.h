@@ -39,6 +39,7 @@ int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 enum Kind : int32_t {
     KIND_LDS = 0,     // one LDS read per addition, lanes strided by 64 samples
     KIND_REGWIN = 1,  // per-lane register window, offsets applied by VGPR index mode
+    KIND_DIRECT = 2,  // operands read straight from memory (no reuse between accumulator rows)
 };
 
 struct Variant {
@@ -47,9 +48,10 @@ struct Variant {
     int32_t items_acc;  // accumulator rows per wave
     int32_t waves;      // wavefronts per work-group
     int32_t kind;
-    int32_t rpw;        // regwin: input rows per wave per staged chunk
+    int32_t rpw;        // input rows per wave per staged chunk (direct: rows in flight)
     int32_t nwr;        // regwin: window registers per lane
-    int32_t kmax;       // regwin: max 64-sample pieces per staged row (wcap <= 64*kmax)
+    int32_t kmax;       // max 64-sample pieces per staged row (wcap <= 64*kmax); 0: direct staging
+    float rate;         // sustained additions per second (1e12) on an Apertif-shaped forward, MI355X
     int32_t tt() const { return 64 * items_t; }
     int32_t ta() const { return items_acc * waves; }
 };

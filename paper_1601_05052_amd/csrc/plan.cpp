@@ -72,7 +72,7 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
     L->n_tiles = n_tiles;
     if (build) {
         L->base.resize((size_t)n_tiles * R);
-        if (v.kind == KIND_LDS)
+        if (v.kind != KIND_REGWIN)
             L->rel.resize((size_t)n_tiles * R * TA);
         else {
             L->wrec.resize((size_t)n_tiles * R * v.waves);
@@ -93,7 +93,7 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
             max_spread = std::max(max_spread, hi - lo);
             if (build)
                 L->base[(size_t)k * R + r] = lo;
-            if (v.kind == KIND_LDS) {
+            if (v.kind != KIND_REGWIN) {
                 if (build)
                     for (int32_t j = 0; j < TA; ++j)
                         L->rel[((size_t)k * R + r) * TA + j] = offset_of(p, direction, r, std::min(A - 1, k * TA + j)) - lo;
@@ -131,7 +131,11 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
     if (!ok)
         return;
     const int64_t lds_limit = 160 * 1024;
-    if (v.kind == KIND_LDS && v.kmax > 0) {
+    if (v.kind == KIND_DIRECT) {
+        L->wcap = 0;
+        L->rows_per_chunk = 0;
+        L->lds_bytes = 0;
+    } else if (v.kind == KIND_LDS && v.kmax > 0) {
         // Prefetched staging: rows padded to whole 64-sample pieces, two buffers.
         const int64_t w64 = ((int64_t)TT + max_spread + 63) & ~int64_t(63);
         const int64_t rows = (int64_t)v.waves * v.rpw;
@@ -259,8 +263,12 @@ static double estimate_seconds(const dd_plan *p, int direction, const Variant &v
     const int64_t n_t = direction == DD_FORWARD ? p->S : p->T_in;
     const double tiles = static_cast<double>((n_t + v.tt() - 1) / v.tt()) * ((A + v.ta() - 1) / v.ta());
     const double staged = tiles * R * static_cast<double>(wcap);
-    const double add_rate = v.kind == KIND_REGWIN ? 30e12 : 6e12;
-    return adds / add_rate + staged / 0.8e12;
+    if (v.kind == KIND_DIRECT) {
+        // one 4-byte read per (row, accumulator row, sample) from L2 / HBM
+        const double reads = static_cast<double>(R) * A * static_cast<double>(n_t);
+        return reads * 4.0 / 3e12;
+    }
+    return adds / (static_cast<double>(v.rate) * 1e12) + staged / 2e12;
 }
 
 int32_t best_by_model(const dd_plan *p, int direction, const int32_t *cand, int32_t n_cand) {

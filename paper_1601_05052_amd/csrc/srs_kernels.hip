@@ -32,14 +32,14 @@ __global__ void __launch_bounds__(64 * NW)
     dev::srs_tile_lds<TIn, IT, TDW, NW>(in, out, rel, base, d, tile_t, tile_a, lds);
 }
 
-template <typename TIn, int IT, int TDW, int NW, int RPW, int KMAX, bool FULL>
+template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX, bool FULL>
 __global__ void __launch_bounds__(64 * NW)
     srs_regwin_kernel(const TIn *__restrict__ in, float *__restrict__ out, const int32_t *__restrict__ base,
                       const int32_t *__restrict__ wrec, const int32_t *__restrict__ woff, SrsDims d) {
     extern __shared__ __attribute__((aligned(16))) float lds_rw[];
     int32_t tile_t, tile_a;
     dev::tile_of_block(d, tile_t, tile_a);
-    dev::srs_tile_regwin<TIn, IT, TDW, NW, RPW, KMAX, FULL>(in, out, base, wrec, woff, d, tile_t, tile_a, lds_rw);
+    dev::srs_tile_regwin<TIn, IT, TDW, NWR, NW, RPW, KMAX, FULL>(in, out, base, wrec, woff, d, tile_t, tile_a, lds_rw);
 }
 
 template <typename TIn, int IT, int TDW, int NW, int RPW, int KMAX>
@@ -50,6 +50,15 @@ __global__ void __launch_bounds__(64 * NW)
     int32_t tile_t, tile_a;
     dev::tile_of_block(d, tile_t, tile_a);
     dev::srs_tile_ldsp<TIn, IT, TDW, NW, RPW, KMAX>(in, out, rel, base, d, tile_t, tile_a, lds_p);
+}
+
+template <typename TIn, int IT, int NW, int U>
+__global__ void __launch_bounds__(64 * NW)
+    srs_direct_kernel(const TIn *__restrict__ in, float *__restrict__ out, const int32_t *__restrict__ rel,
+                      const int32_t *__restrict__ base, SrsDims d) {
+    int32_t tile_t, tile_a;
+    dev::tile_of_block(d, tile_t, tile_a);
+    dev::srs_tile_direct<TIn, IT, NW, U>(in, out, rel, base, d, tile_t, tile_a);
 }
 
 using LaunchFn = hipError_t (*)(const SrsArgs &, const SrsDims &, uint32_t, size_t, hipStream_t);
@@ -71,9 +80,9 @@ hipError_t launch_lds(const SrsArgs &a, const SrsDims &d, uint32_t blocks, size_
     return hipGetLastError();
 }
 
-template <typename TIn, int IT, int TDW, int NW, int RPW, int KMAX, bool FULL>
+template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX, bool FULL>
 hipError_t launch_regwin(const SrsArgs &a, const SrsDims &d, uint32_t blocks, size_t lds, hipStream_t s) {
-    auto fn = srs_regwin_kernel<TIn, IT, TDW, NW, RPW, KMAX, FULL>;
+    auto fn = srs_regwin_kernel<TIn, IT, TDW, NWR, NW, RPW, KMAX, FULL>;
     hipError_t e = set_lds_limit(reinterpret_cast<const void *>(fn), lds);
     if (e != hipSuccess)
         return e;
@@ -93,53 +102,69 @@ hipError_t launch_ldsp(const SrsArgs &a, const SrsDims &d, uint32_t blocks, size
     return hipGetLastError();
 }
 
+template <typename TIn, int IT, int NW, int U>
+hipError_t launch_direct(const SrsArgs &a, const SrsDims &d, uint32_t blocks, size_t, hipStream_t s) {
+    hipLaunchKernelGGL((srs_direct_kernel<TIn, IT, NW, U>), dim3(blocks), dim3(64 * NW), 0, s,
+                       static_cast<const TIn *>(a.in), a.out, a.rel, a.base, d);
+    return hipGetLastError();
+}
+
 struct VariantImpl {
     Variant v;
     LaunchFn fn[3];  // by input type: f32, f16, u8
 };
 
-#define DD_LDS_VARIANT(ID, IT, TDW, NW)                                                   \
-    {{ID, IT, TDW, NW, KIND_LDS, 0, 0, 0},                                                \
+#define DD_LDS_VARIANT(ID, IT, TDW, NW, RATE)                                             \
+    {{ID, IT, TDW, NW, KIND_LDS, 0, 0, 0, RATE},                                                \
      {launch_lds<float, IT, TDW, NW>, launch_lds<_Float16, IT, TDW, NW>, launch_lds<uint8_t, IT, TDW, NW>}}
 
-#define DD_LDSP_VARIANT(ID, IT, TDW, NW, RPW, KMAX)                                              \
-    {{ID, IT, TDW, NW, KIND_LDS, RPW, 0, KMAX},                                                   \
+#define DD_LDSP_VARIANT(ID, IT, TDW, NW, RPW, KMAX, RATE)                                        \
+    {{ID, IT, TDW, NW, KIND_LDS, RPW, 0, KMAX, RATE},                                                   \
      {launch_ldsp<float, IT, TDW, NW, RPW, KMAX>, launch_ldsp<_Float16, IT, TDW, NW, RPW, KMAX>, \
       launch_ldsp<uint8_t, IT, TDW, NW, RPW, KMAX>}}
 
-#define DD_RW_VARIANT(ID, IT, TDW, NW, RPW, KMAX, FULL)                                                     \
-    {{ID, IT, TDW, NW, KIND_REGWIN, RPW, dev::RegWin<IT, TDW>::NWR, KMAX},                                      \
-     {launch_regwin<float, IT, TDW, NW, RPW, KMAX, FULL>, launch_regwin<_Float16, IT, TDW, NW, RPW, KMAX, FULL>, \
-      launch_regwin<uint8_t, IT, TDW, NW, RPW, KMAX, FULL>}}
+#define DD_DIRECT_VARIANT(ID, IT, NW, U, RATE)                                                            \
+    {{ID, IT, 1, NW, KIND_DIRECT, U, 0, 0, RATE},                                                              \
+     {launch_direct<float, IT, NW, U>, launch_direct<_Float16, IT, NW, U>, launch_direct<uint8_t, IT, NW, U>}}
+
+#define DD_RW_VARIANT(ID, IT, TDW, NWR, NW, RPW, KMAX, FULL, RATE)                                    \
+    {{ID, IT, TDW, NW, KIND_REGWIN, RPW, NWR, KMAX, RATE},                                               \
+     {launch_regwin<float, IT, TDW, NWR, NW, RPW, KMAX, FULL>,                                           \
+      launch_regwin<_Float16, IT, TDW, NWR, NW, RPW, KMAX, FULL>,                                        \
+      launch_regwin<uint8_t, IT, TDW, NWR, NW, RPW, KMAX, FULL>}}
 
 const VariantImpl kImpls[] = {
-    DD_LDS_VARIANT(0, 4, 8, 4),   // 256 samples x 32 rows
-    DD_LDS_VARIANT(1, 4, 4, 4),   // 256 x 16
-    DD_LDS_VARIANT(2, 2, 8, 4),   // 128 x 32
-    DD_LDS_VARIANT(3, 8, 4, 4),   // 512 x 16
-    DD_LDS_VARIANT(4, 4, 16, 4),  // 256 x 64
-    DD_LDS_VARIANT(5, 2, 16, 4),  // 128 x 64
-    DD_LDS_VARIANT(6, 4, 2, 4),   // 256 x 8
-    DD_LDS_VARIANT(7, 4, 1, 4),   // 256 x 4
-    DD_LDS_VARIANT(8, 2, 1, 4),   // 128 x 4
-    DD_LDS_VARIANT(9, 1, 1, 1),   // 64 x 1: no cross-row window, always fits
-    DD_RW_VARIANT(10, 8, 8, 4, 1, 16, false),   // 512 x 32, register window
-    DD_RW_VARIANT(11, 8, 8, 4, 2, 16, false),   // 512 x 32, two rows per wave per chunk
-    DD_RW_VARIANT(12, 8, 4, 4, 2, 16, false),   // 512 x 16
-    DD_RW_VARIANT(13, 16, 4, 4, 1, 24, false),  // 1024 x 16
-    DD_RW_VARIANT(14, 4, 8, 4, 2, 12, false),   // 256 x 32
-    DD_RW_VARIANT(15, 8, 8, 8, 1, 16, false),   // 512 x 64, eight waves
-    DD_RW_VARIANT(16, 8, 16, 4, 1, 16, false),  // 512 x 64, sixteen rows per wave
-    DD_RW_VARIANT(17, 8, 8, 4, 1, 12, false),   // 512 x 32, shorter staging (fewer VGPRs)
-    DD_RW_VARIANT(18, 8, 8, 4, 1, 12, true),    // as 17, whole window loaded per row
-    DD_RW_VARIANT(19, 8, 4, 4, 1, 12, false),   // 512 x 16, short staging
-    DD_LDSP_VARIANT(20, 4, 8, 4, 1, 24),        // 256 x 32, LDS form with prefetched staging
-    DD_LDSP_VARIANT(21, 4, 4, 4, 1, 16),        // 256 x 16
-    DD_LDSP_VARIANT(22, 8, 4, 4, 1, 24),        // 512 x 16
-    DD_LDSP_VARIANT(23, 2, 8, 4, 2, 12),        // 128 x 32
-    DD_LDSP_VARIANT(24, 4, 2, 4, 2, 12),        // 256 x 8
-    DD_LDSP_VARIANT(25, 4, 1, 4, 2, 8),         // 256 x 4
-    DD_LDSP_VARIANT(26, 8, 8, 4, 1, 32),        // 512 x 32
+    DD_LDS_VARIANT(0, 4, 8, 4, 5.4f),   // 256 samples x 32 rows
+    DD_LDS_VARIANT(1, 4, 4, 4, 6.3f),   // 256 x 16
+    DD_LDS_VARIANT(2, 2, 8, 4, 7.1f),   // 128 x 32
+    DD_LDS_VARIANT(3, 8, 4, 4, 3.2f),   // 512 x 16
+    DD_LDS_VARIANT(4, 4, 16, 4, 4.7f),  // 256 x 64
+    DD_LDS_VARIANT(5, 2, 16, 4, 5.3f),  // 128 x 64
+    DD_LDS_VARIANT(6, 4, 2, 4, 3.9f),   // 256 x 8
+    DD_LDS_VARIANT(7, 4, 1, 4, 2.3f),   // 256 x 4
+    DD_LDS_VARIANT(8, 2, 1, 4, 2.9f),   // 128 x 4
+    DD_LDS_VARIANT(9, 1, 1, 1, 0.8f),   // 64 x 1: no cross-row window, always fits
+    DD_RW_VARIANT(10, 8, 8, 40, 4, 1, 16, false, 20.1f),   // 512 x 32, register window; rates: measured T adds/s
+    DD_RW_VARIANT(11, 8, 8, 40, 4, 2, 16, false, 15.1f),   // 512 x 32, two rows per wave per chunk
+    DD_RW_VARIANT(12, 8, 4, 32, 4, 2, 16, false, 10.7f),   // 512 x 16
+    DD_RW_VARIANT(13, 16, 4, 48, 4, 1, 24, false, 18.9f),  // 1024 x 16
+    DD_RW_VARIANT(14, 4, 8, 32, 4, 2, 12, false, 15.7f),   // 256 x 32
+    DD_RW_VARIANT(15, 8, 8, 40, 8, 1, 16, false, 16.2f),   // 512 x 64, eight waves
+    DD_RW_VARIANT(16, 8, 16, 48, 4, 1, 16, false, 15.0f),  // 512 x 64, sixteen rows per wave
+    DD_RW_VARIANT(17, 8, 8, 40, 4, 1, 12, false, 23.0f),   // 512 x 32, shorter staging (fewer VGPRs)
+    DD_RW_VARIANT(18, 8, 8, 40, 4, 1, 12, true, 22.2f),    // as 17, whole window loaded per row
+    DD_RW_VARIANT(19, 8, 4, 32, 4, 1, 12, false, 19.3f),   // 512 x 16, short staging
+    DD_LDSP_VARIANT(20, 4, 8, 4, 1, 24, 10.9f),        // 256 x 32, LDS form with prefetched staging
+    DD_LDSP_VARIANT(21, 4, 4, 4, 1, 16, 11.4f),        // 256 x 16
+    DD_LDSP_VARIANT(22, 8, 4, 4, 1, 24, 11.0f),        // 512 x 16
+    DD_LDSP_VARIANT(23, 2, 8, 4, 2, 12, 9.6f),        // 128 x 32
+    DD_LDSP_VARIANT(24, 4, 2, 4, 2, 12, 10.3f),        // 256 x 8
+    DD_LDSP_VARIANT(25, 4, 1, 4, 2, 8, 7.2f),         // 256 x 4
+    DD_LDSP_VARIANT(26, 8, 8, 4, 1, 32, 9.6f),        // 512 x 32
+    DD_DIRECT_VARIANT(27, 4, 4, 4, 4.8f),             // 256 x 4, operands read straight from memory
+    DD_DIRECT_VARIANT(28, 8, 4, 2, 7.3f),             // 512 x 4
+    DD_RW_VARIANT(29, 8, 4, 44, 4, 1, 12, false, 17.5f),   // 512 x 16, wide window (adjoint)
+    DD_RW_VARIANT(30, 8, 8, 76, 4, 1, 12, false, 20.8f),   // 512 x 32, wide window (adjoint)
 };
 constexpr int32_t kNumImpls = sizeof(kImpls) / sizeof(kImpls[0]);
 

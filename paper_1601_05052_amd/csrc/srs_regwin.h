@@ -83,13 +83,13 @@ __device__ __forceinline__ uint32_t lds_address(const float *p) {
     return static_cast<uint32_t>(reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) float *)p));
 }
 
-template <typename TIn, int IT, int TDW, int NW, int RPW, int KMAX, bool FULL>
+template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX, bool FULL>
 __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, float *__restrict__ out,
                                                 const int32_t *__restrict__ base,
                                                 const int32_t *__restrict__ wrec,
                                                 const int32_t *__restrict__ woff, const SrsDims &d,
                                                 int32_t tile_t, int32_t tile_a, float *lds) {
-    using RW = RegWin<IT, TDW>;
+    using RW = RegWin<IT, TDW, NWR>;
     constexpr int TT = 64 * IT;
     constexpr int TA = TDW * NW;
     constexpr int CR = NW * RPW;  // input rows per chunk
@@ -300,6 +300,62 @@ __device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float 
                 if (t < d.n_t)
                     __builtin_nontemporal_store(acc[k][j], dst + t);
             }
+        }
+    }
+}
+
+// Direct form, for shifted-row sums with no reuse between accumulator rows
+// (e.g. the adjoint of a low-frequency setup, where neighbouring channels'
+// delays differ by thousands of samples): each wave owns one accumulator row
+// and reads every operand straight from memory with bounds-checked buffer
+// loads (lane l: samples t0 + l + 64j, coalesced), U input rows in flight.
+template <typename TIn, int IT, int NW, int U>
+__device__ __forceinline__ void srs_tile_direct(const TIn *__restrict__ in, float *__restrict__ out,
+                                                const int32_t *__restrict__ rel,
+                                                const int32_t *__restrict__ base, const SrsDims &d,
+                                                int32_t tile_t, int32_t tile_a) {
+    constexpr int TT = 64 * IT;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t t0 = static_cast<int64_t>(tile_t) * TT;
+    const int32_t *base_tile = base + static_cast<int64_t>(tile_a) * d.n_rows;
+    const int32_t *rel_tile = rel + static_cast<int64_t>(tile_a) * d.n_rows * NW + wave;
+    const int32_t n_bytes = static_cast<int32_t>(d.in_valid * static_cast<int64_t>(sizeof(TIn)));
+    float acc[IT];
+#pragma unroll
+    for (int j = 0; j < IT; ++j)
+        acc[j] = 0.f;
+    for (int32_t r0 = 0; r0 < d.n_rows; r0 += U) {
+        float v[U][IT];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t r = min(r0 + u, d.n_rows - 1);
+            const int64_t g0 = t0 + __builtin_amdgcn_readfirstlane(base_tile[r]) +
+                               __builtin_amdgcn_readfirstlane(rel_tile[static_cast<int64_t>(r) * NW]);
+            const TIn *rp = in + static_cast<int64_t>(r) * d.in_stride;
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<TIn *>(rp), 0, n_bytes, kBufferFlags);
+#pragma unroll
+            for (int j = 0; j < IT; ++j) {
+                const int64_t g = g0 + lane + 64 * j;
+                const uint32_t off = g >= 0 ? static_cast<uint32_t>(g) * sizeof(TIn) : kOutOfRange;
+                v[u][j] = (r0 + u < d.n_rows) ? buffer_ld<TIn>(rs, off) : 0.f;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < IT; ++j)
+                acc[j] += v[u][j];
+    }
+    const int32_t ag = tile_a * NW + wave;
+    if (ag < d.n_acc) {
+        float *dst = out + static_cast<int64_t>(ag) * d.out_stride;
+#pragma unroll
+        for (int j = 0; j < IT; ++j) {
+            const int64_t t = t0 + lane + 64 * j;
+            if (t < d.n_t)
+                __builtin_nontemporal_store(acc[j], dst + t);
         }
     }
 }

@@ -139,6 +139,11 @@ def test_null_plan_queries():
     assert L.dd_plan_destroy(None) == _lib.DD_OK
     assert L.dd_batch_destroy(None) == _lib.DD_OK
     assert L.dd_batch_create(None, None, 0, 0) == _lib.DD_EINVAL
+    assert L.dd_batch_autotune(None, 0, 0, 1, None, None) == _lib.DD_EINVAL
+    p = Plan.from_setup(synth.TINY)
+    arr = (ctypes.c_void_p * 1)(p.handle.value)
+    assert L.dd_batch_autotune(arr, 1, 2, 0, None, None) == _lib.DD_EINVAL    # reps 0
+    assert L.dd_batch_autotune(arr, 1, 9, 1, None, None) == _lib.DD_EINVAL    # dtype
 
 
 def test_tile_variants_cover_paper_parameters():
@@ -147,8 +152,8 @@ def test_tile_variants_cover_paper_parameters():
     assert len(vs) >= 8
     for i, (vid, it, ia, waves, kind) in enumerate(vs):
         assert vid == i
-        assert it >= 1 and ia >= 1 and 1 <= waves <= 16 and kind in (0, 1)
-    assert {v[4] for v in vs} == {0, 1}, "both the LDS and the register-window kernels are compiled"
+        assert it >= 1 and ia >= 1 and 1 <= waves <= 16 and kind in (0, 1, 2)
+    assert {v[4] for v in vs} == {0, 1, 2}, "LDS, register-window and direct kernels are all compiled"
 
 
 def test_set_tile_rejects_window_too_large():
@@ -172,3 +177,14 @@ def test_fault_injection_alloc(monkeypatch):
     rc = _lib.lib().dd_plan_prepare(p.handle, 0, 0)
     # Without a GPU, hipGetDevice may fail first (DD_EHIP); with one, DD_ENOMEM.
     assert rc in (_lib.DD_ENOMEM, _lib.DD_EHIP)
+
+
+def test_generated_asm_header_is_current():
+    """regwin_asm.h is generated; the committed copy must match its generator."""
+    import importlib.util
+    gen = os.path.join(ROOT, "paper_1601_05052_amd", "csrc", "gen_regwin_asm.py")
+    spec = importlib.util.spec_from_file_location("gen_regwin_asm", gen)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    with open(os.path.join(ROOT, "paper_1601_05052_amd", "csrc", "regwin_asm.h")) as f:
+        assert f.read() == mod.render()
