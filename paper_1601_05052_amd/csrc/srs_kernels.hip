@@ -165,6 +165,8 @@ const VariantImpl kImpls[] = {
     DD_DIRECT_VARIANT(28, 8, 4, 2, 7.3f),             // 512 x 4
     DD_RW_VARIANT(29, 8, 4, 44, 4, 1, 12, false, 17.5f),   // 512 x 16, wide window (adjoint)
     DD_RW_VARIANT(30, 8, 8, 76, 4, 1, 12, false, 20.8f),   // 512 x 32, wide window (adjoint)
+    DD_RW_VARIANT(31, 8, 8, 40, 8, 1, 12, false, 20.0f),   // 512 x 64, eight waves, short staging
+    DD_RW_VARIANT(32, 16, 4, 48, 4, 1, 20, false, 18.0f),  // 1024 x 16, short staging
 };
 constexpr int32_t kNumImpls = sizeof(kImpls) / sizeof(kImpls[0]);
 
