@@ -192,7 +192,7 @@ def extras(torch, dd, stream, steps):
                                  note="forward + adjoint adds of 8 beams per step, autograd incl. loss ops")
     log("fwd+bwd 8 beams: %.3f ms" % ms_fb)
     del xs, ws, gy
-    # batched: 64 uneven beams, one persistent launch
+    # batched: 64 uneven beams, one graph launch (one kernel per tile variant in use)
     for dt, code in (("u8", dd.DD_U8), ("f16", dd.DD_F16)):
         beams = synth.batched_beams()
         plans = [dd.Plan.from_setup(b) for b in beams]
@@ -206,7 +206,8 @@ def extras(torch, dd, stream, steps):
                 dd.dedisperse(x, p, out=o)
         ms_s, _ = timed(torch, singles, max(2, steps // 4), 1, stream)
         res["batched64_" + dt] = dict(ms=ms_b, gflops=batch.adds / (ms_b * 1e-3) / 1e9,
-                                      per_beam_launches_ms=ms_s, adds=batch.adds)
+                                      per_beam_launches_ms=ms_s, adds=batch.adds,
+                                      kernels_in_graph=len(set(batch.variants())))
         log("batched %s: %.3f ms (%.1f GFLOP/s), per-beam launches %.3f ms" % (dt, ms_b, batch.adds / (ms_b * 1e-3) / 1e9, ms_s))
         del xs, outs, batch
         torch.cuda.empty_cache()

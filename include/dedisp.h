@@ -168,32 +168,44 @@ int dd_autotune(dd_plan *plan, dd_direction direction, dd_dtype in_type, int32_t
 /* ---------------------------------------------------------------- batches */
 
 /* Many independent beams (Sec. III-A treats one beam without loss of
- * generality; beams are independent) dedispersed by ONE persistent kernel
- * launch.  The batch keeps pointers to the plans, which must outlive it;
- * every beam uses in_type.  Work items are ordered by cost (largest first)
- * and handed out through a device counter. */
+ * generality; beams are independent) dedispersed by ONE HIP graph launch.
+ * Each beam uses the forward tile variant its plan would use alone (forced
+ * by dd_plan_set_tile, tuned by dd_autotune / dd_batch_autotune, else the
+ * cost model's choice); beams sharing a variant are served by one launch of
+ * that variant's multi-beam kernel, whose work list deals every beam's tiles
+ * evenly over the XCDs.  The batch keeps pointers to the plans, which must
+ * outlive it; every beam uses in_type.  Variant choices are read here: later
+ * tuning of the plans does not change an existing batch.  At most 96 beams,
+ * each under 2^24 tiles.
+ *   DD_EINVAL        NULL argument, n_beams out of range, unknown dtype
+ *   DD_EUNSUPPORTED  a beam has no fitting variant or too many tiles
+ *   DD_ENOMEM / DD_EHIP  device allocation or graph construction failed */
 int dd_batch_create(dd_batch **out, const dd_plan *const *plans, int32_t n_beams,
                     dd_dtype in_type);
 
-/* Auto-tune each plan's forward tile for the batch kernel (Sec. IV-A), over
- * the variants the batch kernel compiles, timing single-beam launches of each
- * plan on private scratch buffers (allocated and freed here).  The choice is
- * stored in the plan and used by the next dd_batch_create; cache_path as in
- * dd_autotune.  Synchronises `stream`. */
+/* Auto-tune each plan's forward tile (Sec. IV-A) for in_type over every
+ * variant, as dd_autotune does; plans of identical shape are timed once per
+ * call.  The choice is stored in each plan (so single-beam calls use it too)
+ * and read by the next dd_batch_create; cache_path as in dd_autotune.
+ * Scratch buffers are allocated and freed here.  Synchronises `stream`. */
 int dd_batch_autotune(dd_plan *const *plans, int32_t n_beams, dd_dtype in_type, int32_t reps,
                       const char *cache_path, void *stream);
 
 /* Run every beam: for beam b, the forward of plans[b] on d_in[b] (row stride
  * in_strides[b] elements) into d_out[b] (row stride out_strides[b]).  The
  * pointer arrays are host arrays of n_beams device pointers; they are copied
- * into a device descriptor table on `stream` before the launch, so the host
- * arrays may be reused when the call returns.  Same per-beam requirements
- * as dd_dedisperse. */
+ * into the graph's kernel arguments before the launch, so the host arrays
+ * may be reused when the call returns.  Same per-beam requirements as
+ * dd_dedisperse; must be called with the batch's device current.  Runs that
+ * overlap on one batch from several host threads race on its arguments. */
 int dd_batch_run(dd_batch *batch, const void *const *d_in, const int64_t *in_strides,
                  float *const *d_out, const int64_t *out_strides, void *stream);
 
 /* Total additions (sum over beams of n_dm*n_samples*n_channels). */
 int dd_batch_adds(const dd_batch *batch, double *adds);
+
+/* The tile variant each beam runs with (variants: n_beams entries). */
+int dd_batch_variants(const dd_batch *batch, int32_t *variants);
 
 int dd_batch_destroy(dd_batch *batch);
 

@@ -215,7 +215,7 @@ Dedisperse = _LazyAutograd()
 
 
 class Batch:
-    """Many beams, one persistent launch (see dd_batch_create)."""
+    """Many beams, one graph launch (see dd_batch_create)."""
 
     def __init__(self, plans: Sequence[Plan], dtype: int = DD_F32, tune: bool = False, reps: int = 2,
                  cache_path: Optional[str] = None, device=None):
@@ -232,6 +232,12 @@ class Batch:
         adds = ctypes.c_double()
         check(_lib.lib().dd_batch_adds(h, ctypes.byref(adds)))
         self.adds = adds.value
+
+    def variants(self):
+        """Tile variant of each beam."""
+        v = (ctypes.c_int32 * len(self.plans))()
+        check(_lib.lib().dd_batch_variants(self._h, v))
+        return list(v)
 
     def run(self, xs, outs=None):
         torch = _torch()

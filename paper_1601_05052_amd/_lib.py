@@ -46,10 +46,25 @@ SIGNATURES = {
     "dd_batch_autotune": [P(vp), i32, ctypes.c_int, i32, ctypes.c_char_p, vp],
     "dd_batch_run": [vp, P(vp), P(i64), P(vp), P(i64), vp],
     "dd_batch_adds": [vp, P(dbl)],
+    "dd_batch_variants": [vp, P(i32)],
     "dd_batch_destroy": [vp],
     "dd_last_error": [],
     "dd_version": [],
 }
+
+
+def _load_torch_runtime() -> None:
+    """Load PyTorch (and with it PyTorch's HIP runtime) before libdedisp.
+
+    Both runtimes carry the soname libamdhip64.so.7: if PyTorch's copy is
+    already in the process, libdedisp binds to it, so the process has one HIP
+    runtime and PyTorch's streams and allocations are valid handles for the
+    library.  Loaded the other way round, the process would hold two HIP/HSA
+    runtimes, and the one initialised second finds no device."""
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
 
 
 def lib():
@@ -57,6 +72,7 @@ def lib():
     there is no fallback implementation."""
     global _LIB
     if _LIB is None:
+        _load_torch_runtime()
         path = library_path()
         if not os.path.exists(path):
             raise ImportError("libdedisp.so is not built (%s); run: python -m paper_1601_05052_amd.build"

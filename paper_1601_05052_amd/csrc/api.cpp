@@ -17,10 +17,7 @@ bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
 }
 
 int resolve_variant(const dd_plan *p, int direction, int32_t in_type, const Variant **out) {
-    int32_t id = choose_variant(p, direction, in_type);
-    if (id == -2)
-        id = default_variant(p, direction, in_type);
-    const Variant *v = find_variant(id);
+    const Variant *v = find_variant(resolved_variant(p, direction, in_type));
     if (!v)
         return fail(DD_EUNSUPPORTED, "no tile variant can serve this plan");
     *out = v;

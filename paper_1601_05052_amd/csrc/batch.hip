@@ -1,132 +1,75 @@
-// Batched dedispersion: many independent beams (Sclocco et al., Sec. III-A,
-// "all results can be applied to the case of multiple beams"; Sec. II, beams
-// are independent) in ONE persistent kernel launch, replayed from a HIP graph.
+// Batched dedispersion: many independent beams (the method is stated for one
+// beam without loss of generality, and beams share nothing, Sec. II / III-A)
+// run from ONE HIP graph launch.
 //
-// Work items are (beam, DM tile, time tile) triples ordered by cost, largest
-// first, and handed out by an atomic counter; every beam keeps its own tile
-// shape (chosen per plan, e.g. by dd_autotune) from the family of 4-wave
-// variants compiled into the kernel.  Per-run pointers travel as a by-value
-// kernel argument that dd_batch_run patches into the graph before launch, so
-// no host-to-device copy is needed per run.
+// Every beam keeps the tile variant its plan would use on its own (forced,
+// tuned by dd_autotune / dd_batch_autotune, or the cost model's choice).
+// Beams that share a variant form a group served by one launch of that
+// variant's multi-beam kernel, so each kernel keeps the register footprint
+// and occupancy of the single-beam kernel.  The groups' launches are chained
+// in the graph; per-run pointers travel as a by-value kernel argument that
+// dd_batch_run patches into the instantiated graph before each launch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <numeric>
 #include <vector>
 
+#include "batch_desc.h"
 #include "internal.h"
-#include "srs_regwin.h"
-#include "srs_tile.h"
 
 namespace dd {
 namespace {
 
-constexpr int kMaxBeams = 96;
-
-struct BeamPtrs {
-    const void *in;
-    float *out;
-    int64_t in_stride;
-    int64_t out_stride;
+struct Group {
+    int32_t variant = -1;
+    std::vector<int32_t> beams;
+    const void *fn = nullptr;
+    uint32_t threads = 0;
+    uint32_t grid = 0;
+    uint32_t item_offset = 0;
+    size_t lds = 0;
+    // Kernel-argument storage (kernelParams point here).
+    const BeamDesc *a_descs = nullptr;
+    const uint32_t *a_items = nullptr;
+    void *params[3] = {};
+    hipGraphNode_t node = nullptr;
 };
 
-struct BatchPtrs {
-    BeamPtrs b[kMaxBeams];
-};
-
-struct BeamDesc {
-    const int32_t *rel;
-    const int32_t *base;
-    const int32_t *wrec;
-    const int32_t *woff;
-    dev::SrsDims d;
-    int32_t slot;
-    int32_t pad;
-};
-
-}  // namespace
-}  // namespace dd
-
-namespace dd {
-
-// The batch kernel's tile family: 4-wave variants whose register footprints
-// are close, so one kernel serves them all at the occupancy of the largest.
-// Index = slot, value = variant id (see srs_kernels.hip).
-const int32_t kBatchFamily[] = {17, 19, 14, 21, 20, 24, 25, 7};
-const int32_t kBatchFamilySize = sizeof(kBatchFamily) / sizeof(kBatchFamily[0]);
-
-int32_t batch_slot_of_variant(int32_t v) {
-    for (int32_t s = 0; s < kBatchFamilySize; ++s)
-        if (kBatchFamily[s] == v)
-            return s;
-    return -1;
-}
-
-}  // namespace dd
-
-namespace dd {
-namespace {
-
-int32_t slot_of_variant(int32_t v) { return batch_slot_of_variant(v); }
-
-__global__ void reset_counter(uint32_t *counter) { *counter = 0u; }
-
-template <typename TIn>
-__global__ void __launch_bounds__(256)
-    batch_kernel(BatchPtrs ptrs, const BeamDesc *__restrict__ descs, const uint32_t *__restrict__ items,
-                 uint32_t n_items, uint32_t *__restrict__ counter) {
-    extern __shared__ __attribute__((aligned(16))) float lds[];
-    __shared__ uint32_t s_item;
-    for (;;) {
-        if (threadIdx.x == 0)
-            s_item = atomicAdd(counter, 1u);
-        __syncthreads();
-        const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();  // everyone has read s_item before it is reused
-        if (item >= n_items)
-            break;  // every work-group leaves once the list is exhausted
-        const uint32_t w = items[item];
-        const uint32_t beam = w >> 24, tile = w & 0xffffffu;
-        const BeamDesc &bd = descs[beam];
-        const BeamPtrs bp = ptrs.b[beam];
-        dev::SrsDims d = bd.d;
-        d.in_stride = bp.in_stride;
-        d.out_stride = bp.out_stride;
-        const int32_t tile_a = static_cast<int32_t>(tile % static_cast<uint32_t>(d.n_acc_tiles));
-        const int32_t tile_t = static_cast<int32_t>(tile / static_cast<uint32_t>(d.n_acc_tiles));
-        const TIn *in = static_cast<const TIn *>(bp.in);
-        // Slot -> tile routine; must match kBatchFamily.
-        switch (bd.slot) {
-        case 0:
-            dev::srs_tile_regwin<TIn, 8, 8, 40, 4, 1, 12, false>(in, bp.out, bd.base, bd.wrec, bd.woff, d, tile_t,
-                                                               tile_a, lds);
-            break;
-        case 1:
-            dev::srs_tile_regwin<TIn, 8, 4, 32, 4, 1, 12, false>(in, bp.out, bd.base, bd.wrec, bd.woff, d, tile_t,
-                                                               tile_a, lds);
-            break;
-        case 2:
-            dev::srs_tile_regwin<TIn, 4, 8, 32, 4, 2, 12, false>(in, bp.out, bd.base, bd.wrec, bd.woff, d, tile_t,
-                                                               tile_a, lds);
-            break;
-        case 3: dev::srs_tile_ldsp<TIn, 4, 4, 4, 1, 16>(in, bp.out, bd.rel, bd.base, d, tile_t, tile_a, lds); break;
-        case 4: dev::srs_tile_ldsp<TIn, 4, 8, 4, 1, 24>(in, bp.out, bd.rel, bd.base, d, tile_t, tile_a, lds); break;
-        case 5: dev::srs_tile_ldsp<TIn, 4, 2, 4, 2, 12>(in, bp.out, bd.rel, bd.base, d, tile_t, tile_a, lds); break;
-        case 6: dev::srs_tile_ldsp<TIn, 4, 1, 4, 2, 8>(in, bp.out, bd.rel, bd.base, d, tile_t, tile_a, lds); break;
-        default:  // direct staging: fits spreads up to the LDS size
-            dev::srs_tile_lds<TIn, 4, 1, 4>(in, bp.out, bd.rel, bd.base, d, tile_t, tile_a, lds);
-            break;
+// Work list of one group.  Work-groups are dealt to the 8 XCDs round-robin
+// (work-group g runs on XCD g % 8), so the list gives XCD x the entries
+// g = 8j + x.  Every beam's logical tiles (accumulator tile fastest) are cut
+// into 8 contiguous runs, one per XCD -- the same order as the single-beam
+// kernel, so an XCD's resident work-groups share input windows in its L2 --
+// and XCD x walks run x of each beam in turn, costliest beams first.  The
+// remainders of uneven beams are dealt to XCDs in rotation; slots past the
+// end of an XCD's list hold kNoItem.
+std::vector<uint32_t> group_items(const std::vector<int32_t> &beams, const std::vector<BeamDesc> &descs) {
+    std::vector<std::vector<uint32_t>> per_xcd(8);
+    uint32_t rot = 0;
+    for (int32_t b : beams) {
+        const uint32_t n = static_cast<uint32_t>(descs[b].d.n_t_tiles) * static_cast<uint32_t>(descs[b].d.n_acc_tiles);
+        const uint32_t per = n / 8u, extra = n % 8u;
+        uint32_t start = 0;
+        for (uint32_t x = 0; x < 8u; ++x) {
+            const uint32_t len = per + (((x + 8u - rot) % 8u) < extra ? 1u : 0u);
+            for (uint32_t k = 0; k < len; ++k)
+                per_xcd[x].push_back((static_cast<uint32_t>(b) << 24) | (start + k));
+            start += len;
         }
+        rot = (rot + extra) % 8u;
     }
-}
-
-const void *batch_fn(int32_t in_type) {
-    switch (in_type) {
-    case DD_F32: return reinterpret_cast<const void *>(batch_kernel<float>);
-    case DD_F16: return reinterpret_cast<const void *>(batch_kernel<_Float16>);
-    default: return reinterpret_cast<const void *>(batch_kernel<uint8_t>);
-    }
+    size_t longest = 0;
+    for (const auto &l : per_xcd)
+        longest = std::max(longest, l.size());
+    std::vector<uint32_t> items(8 * longest, kNoItem);
+    for (uint32_t x = 0; x < 8u; ++x)
+        for (size_t j = 0; j < per_xcd[x].size(); ++j)
+            items[8 * j + x] = per_xcd[x][j];
+    return items;
 }
 
 }  // namespace
@@ -139,25 +82,14 @@ struct dd_batch {
     int32_t n_beams = 0;
     int32_t in_type = DD_F32;
     std::vector<const dd_plan *> plans;
+    std::vector<int32_t> beam_variant;
     double adds = 0;
     BeamDesc *d_descs = nullptr;
     uint32_t *d_items = nullptr;
-    uint32_t *d_counter = nullptr;
-    uint32_t n_items = 0;
-    uint32_t grid = 0;
-    size_t lds = 0;
+    std::vector<std::unique_ptr<Group>> groups;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraphNode_t node = nullptr;
-    // Kernel-argument storage for the batch node (kernelParams points here).
-    BatchPtrs ptrs;
-    const BeamDesc *a_descs = nullptr;
-    const uint32_t *a_items = nullptr;
-    uint32_t a_n_items = 0;
-    uint32_t *a_counter = nullptr;
-    void *params[5] = {};
-    uint32_t *r_counter = nullptr;
-    void *r_params[1] = {};
+    BatchPtrs ptrs;  // per-run pointers, copied into every node's arguments
 };
 
 static void batch_free(dd_batch *b) {
@@ -173,7 +105,6 @@ static void batch_free(dd_batch *b) {
         (void)hipGraphDestroy(b->graph);
     (void)hipFree(b->d_descs);
     (void)hipFree(b->d_items);
-    (void)hipFree(b->d_counter);
     if (have)
         (void)hipSetDevice(cur);
     delete b;
@@ -199,23 +130,21 @@ extern "C" int dd_batch_create(dd_batch **out, const dd_plan *const *plans, int3
     B->n_beams = n_beams;
     B->in_type = in_type;
     B->plans.assign(plans, plans + n_beams);
+    B->beam_variant.assign(n_beams, -1);
 
     std::vector<BeamDesc> descs(n_beams);
-    std::vector<uint64_t> cost(n_beams);
-    uint64_t total_items = 0;
+    std::vector<size_t> lds(n_beams, 0);
+    std::map<int32_t, size_t> group_of;  // variant id -> index in B->groups
     for (int32_t b = 0; b < n_beams; ++b) {
         const dd_plan *p = plans[b];
         B->adds += static_cast<double>(p->D) * static_cast<double>(p->S) * p->C;
-        // The plan's batch-tuned choice, else its own choice if it is in the
-        // batch family, else the family member the cost model prefers.
-        int32_t vid = batch_variant(p, in_type);
-        if (vid < 0) {
+        const Variant *v = find_variant(resolved_variant(p, DD_FORWARD, in_type));
+        if (!v) {
             batch_free(B);
-            return fail(DD_EUNSUPPORTED, "beam %d: no batched tile variant fits its delay spread", b);
+            return fail(DD_EUNSUPPORTED, "beam %d: no tile variant can serve this plan", b);
         }
-        const Variant &v = *find_variant(vid);
         SrsArgs a;
-        int rc = make_args(p, DD_FORWARD, v, nullptr, 0, nullptr, 0, &a);
+        int rc = make_args(p, DD_FORWARD, *v, nullptr, 0, nullptr, 0, &a);
         if (rc != DD_OK) {
             batch_free(B);
             return rc;
@@ -232,54 +161,68 @@ extern "C" int dd_batch_create(dd_batch **out, const dd_plan *const *plans, int3
         bd.d.n_rows = a.n_rows;
         bd.d.wcap = a.wcap;
         bd.d.rows_per_chunk = a.rows_per_chunk;
-        bd.d.n_t_tiles = static_cast<int32_t>((a.n_t + v.tt() - 1) / v.tt());
-        bd.d.n_acc_tiles = (a.n_acc + v.ta() - 1) / v.ta();
-        bd.slot = slot_of_variant(vid);
+        bd.d.n_t_tiles = static_cast<int32_t>((a.n_t + v->tt() - 1) / v->tt());
+        bd.d.n_acc_tiles = (a.n_acc + v->ta() - 1) / v->ta();
         const uint64_t n = static_cast<uint64_t>(bd.d.n_t_tiles) * bd.d.n_acc_tiles;
         if (n >= (1u << 24)) {
             batch_free(B);
             return fail(DD_EUNSUPPORTED, "beam %d has %llu tiles (limit 2^24)", b, (unsigned long long)n);
         }
-        total_items += n;
-        cost[b] = static_cast<uint64_t>(v.tt()) * v.ta() * p->C;
-        B->lds = std::max(B->lds, static_cast<size_t>(a.lds_bytes));
+        lds[b] = static_cast<size_t>(a.lds_bytes);
+        B->beam_variant[b] = v->id;
+        auto it = group_of.find(v->id);
+        if (it == group_of.end()) {
+            it = group_of.emplace(v->id, B->groups.size()).first;
+            B->groups.emplace_back(new Group());
+            B->groups.back()->variant = v->id;
+        }
+        B->groups[it->second]->beams.push_back(b);
     }
-    if (total_items >= (1ull << 32)) {
-        batch_free(B);
-        return fail(DD_EUNSUPPORTED, "too many work items");
-    }
-    // Work list: beams by descending per-item cost (longest items first).
-    std::vector<int32_t> order(n_beams);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return cost[x] > cost[y]; });
-    std::vector<uint32_t> items;
-    items.reserve(total_items);
-    for (int32_t b : order) {
-        const uint32_t n = static_cast<uint32_t>(descs[b].d.n_t_tiles) * descs[b].d.n_acc_tiles;
-        for (uint32_t t = 0; t < n; ++t)
-            items.push_back((static_cast<uint32_t>(b) << 24) | t);
-    }
-    B->n_items = static_cast<uint32_t>(items.size());
 
-    const void *fn = batch_fn(in_type);
-    hipError_t e = hipSuccess;
-    if (B->lds > 65536)
-        e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(B->lds));
-    int per_cu = 0, n_cu = 0;
-    if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, B->lds);
-    if (e == hipSuccess)
-        e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, B->device);
-    if (e != hipSuccess) {
-        batch_free(B);
-        return fail(DD_EHIP, "occupancy query failed: %s", hipGetErrorString(e));
+    // Work lists; groups with the most additions first.
+    std::vector<uint32_t> items;
+    std::vector<double> group_adds(B->groups.size(), 0.0);
+    for (size_t g = 0; g < B->groups.size(); ++g) {
+        Group &G = *B->groups[g];
+        for (int32_t b : G.beams)
+            group_adds[g] += static_cast<double>(plans[b]->D) * static_cast<double>(plans[b]->S) * plans[b]->C;
+        std::stable_sort(G.beams.begin(), G.beams.end(),
+                         [&](int32_t x, int32_t y) { return descs[x].d.n_rows > descs[y].d.n_rows; });
     }
-    per_cu = std::max(per_cu, 1);
-    B->grid = static_cast<uint32_t>(std::min<uint64_t>(static_cast<uint64_t>(per_cu) * n_cu, B->n_items));
+    std::vector<size_t> gorder(B->groups.size());
+    std::iota(gorder.begin(), gorder.end(), 0);
+    std::stable_sort(gorder.begin(), gorder.end(), [&](size_t x, size_t y) { return group_adds[x] > group_adds[y]; });
+    std::vector<std::unique_ptr<Group>> sorted;
+    for (size_t g : gorder)
+        sorted.push_back(std::move(B->groups[g]));
+    B->groups = std::move(sorted);
+    for (auto &gp : B->groups) {
+        Group &G = *gp;
+        const Variant &v = *find_variant(G.variant);
+        std::vector<uint32_t> gi = group_items(G.beams, descs);
+        if (items.size() + gi.size() >= (1ull << 32) || gi.size() > 0x7fffffffu) {
+            batch_free(B);
+            return fail(DD_EUNSUPPORTED, "too many work items");
+        }
+        G.item_offset = static_cast<uint32_t>(items.size());
+        G.grid = static_cast<uint32_t>(gi.size());
+        items.insert(items.end(), gi.begin(), gi.end());
+        G.fn = multi_kernel(v, in_type);
+        G.threads = static_cast<uint32_t>(64 * v.waves);
+        for (int32_t b : G.beams)
+            G.lds = std::max(G.lds, lds[b]);
+        if (G.lds > 65536) {
+            hipError_t e = hipFuncSetAttribute(G.fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               static_cast<int>(G.lds));
+            if (e != hipSuccess) {
+                batch_free(B);
+                return fail(DD_EHIP, "setting the LDS limit failed: %s", hipGetErrorString(e));
+            }
+        }
+    }
 
     if (hipMalloc(&B->d_descs, descs.size() * sizeof(BeamDesc)) != hipSuccess ||
-        hipMalloc(&B->d_items, items.size() * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc(&B->d_counter, sizeof(uint32_t)) != hipSuccess) {
+        hipMalloc(&B->d_items, items.size() * sizeof(uint32_t)) != hipSuccess) {
         (void)hipGetLastError();
         batch_free(B);
         return fail(DD_ENOMEM, "device allocation for the batch failed");
@@ -290,38 +233,32 @@ extern "C" int dd_batch_create(dd_batch **out, const dd_plan *const *plans, int3
         return fail(DD_EHIP, "upload of the batch tables failed");
     }
 
-    // Graph: counter reset (a kernel, not a memset node) -> persistent kernel.
+    // Graph: one kernel node per group, chained.
     std::memset(&B->ptrs, 0, sizeof(B->ptrs));
-    B->a_descs = B->d_descs;
-    B->a_items = B->d_items;
-    B->a_n_items = B->n_items;
-    B->a_counter = B->d_counter;
-    B->params[0] = &B->ptrs;
-    B->params[1] = &B->a_descs;
-    B->params[2] = &B->a_items;
-    B->params[3] = &B->a_n_items;
-    B->params[4] = &B->a_counter;
-    B->r_counter = B->d_counter;
-    B->r_params[0] = &B->r_counter;
-
-    hipGraphNode_t reset = nullptr;
-    hipKernelNodeParams rp;
-    std::memset(&rp, 0, sizeof(rp));
-    rp.func = reinterpret_cast<void *>(reset_counter);
-    rp.gridDim = dim3(1);
-    rp.blockDim = dim3(1);
-    rp.kernelParams = B->r_params;
-    hipKernelNodeParams kp;
-    std::memset(&kp, 0, sizeof(kp));
-    kp.func = const_cast<void *>(fn);
-    kp.gridDim = dim3(B->grid);
-    kp.blockDim = dim3(256);
-    kp.sharedMemBytes = static_cast<unsigned int>(B->lds);
-    kp.kernelParams = B->params;
-    if ((e = hipGraphCreate(&B->graph, 0)) != hipSuccess ||
-        (e = hipGraphAddKernelNode(&reset, B->graph, nullptr, 0, &rp)) != hipSuccess ||
-        (e = hipGraphAddKernelNode(&B->node, B->graph, &reset, 1, &kp)) != hipSuccess ||
-        (e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0)) != hipSuccess) {
+    hipError_t e = hipGraphCreate(&B->graph, 0);
+    hipGraphNode_t prev = nullptr;
+    for (auto &gp : B->groups) {
+        if (e != hipSuccess)
+            break;
+        Group &G = *gp;
+        G.a_descs = B->d_descs;
+        G.a_items = B->d_items + G.item_offset;
+        G.params[0] = &B->ptrs;
+        G.params[1] = &G.a_descs;
+        G.params[2] = &G.a_items;
+        hipKernelNodeParams kp;
+        std::memset(&kp, 0, sizeof(kp));
+        kp.func = const_cast<void *>(G.fn);
+        kp.gridDim = dim3(G.grid);
+        kp.blockDim = dim3(G.threads);
+        kp.sharedMemBytes = static_cast<unsigned int>(G.lds);
+        kp.kernelParams = G.params;
+        e = hipGraphAddKernelNode(&G.node, B->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+        prev = G.node;
+    }
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
         batch_free(B);
         return fail(DD_EHIP, "building the batch graph failed: %s", hipGetErrorString(e));
     }
@@ -358,15 +295,27 @@ extern "C" int dd_batch_run(dd_batch *B, const void *const *d_in, const int64_t 
         B->ptrs.b[b].in_stride = in_strides[b];
         B->ptrs.b[b].out_stride = out_strides[b];
     }
-    hipKernelNodeParams kp;
-    std::memset(&kp, 0, sizeof(kp));
-    kp.func = const_cast<void *>(batch_fn(B->in_type));
-    kp.gridDim = dim3(B->grid);
-    kp.blockDim = dim3(256);
-    kp.sharedMemBytes = static_cast<unsigned int>(B->lds);
-    kp.kernelParams = B->params;
-    DD_HIP_TRY(hipGraphExecKernelNodeSetParams(B->exec, B->node, &kp));
+    for (auto &gp : B->groups) {
+        const Group &G = *gp;
+        hipKernelNodeParams kp;
+        std::memset(&kp, 0, sizeof(kp));
+        kp.func = const_cast<void *>(G.fn);
+        kp.gridDim = dim3(G.grid);
+        kp.blockDim = dim3(G.threads);
+        kp.sharedMemBytes = static_cast<unsigned int>(G.lds);
+        kp.kernelParams = const_cast<void **>(G.params);
+        DD_HIP_TRY(hipGraphExecKernelNodeSetParams(B->exec, G.node, &kp));
+    }
     DD_HIP_TRY(hipGraphLaunch(B->exec, static_cast<hipStream_t>(stream)));
+    return DD_OK;
+}
+
+extern "C" int dd_batch_variants(const dd_batch *B, int32_t *variants) {
+    clear_error();
+    if (!B || !variants)
+        return fail(DD_EINVAL, "NULL argument");
+    for (int32_t b = 0; b < B->n_beams; ++b)
+        variants[b] = B->beam_variant[b];
     return DD_OK;
 }
 

@@ -82,6 +82,9 @@ enum InType : int32_t { IN_F32 = DD_F32, IN_F16 = DD_F16, IN_U8 = DD_U8 };
 
 // Launch one shifted-row-sum problem with the given variant.
 hipError_t launch_srs(const Variant &v, int32_t in_type, const SrsArgs &a, hipStream_t stream);
+// The variant's multi-beam kernel (arguments: BatchPtrs by value, const
+// BeamDesc *, const uint32_t *items; 64 * waves threads per work-group).
+const void *multi_kernel(const Variant &v, int32_t in_type);
 
 // Host-side layout of one (direction, variant) on one plan.
 struct Layout {
@@ -126,7 +129,6 @@ struct dd_plan {
     // forced tile per (direction, dtype); -1 = automatic
     int32_t forced[2][3] = {{-1, -1, -1}, {-1, -1, -1}};
     int32_t tuned[2][3] = {{-1, -1, -1}, {-1, -1, -1}};
-    int32_t tuned_batch[3] = {-1, -1, -1};  // forward, per input type, within the batch family
 };
 
 namespace dd {
@@ -140,13 +142,10 @@ int32_t default_variant(const dd_plan *p, int direction, int32_t in_type);
 // Whether variant v can serve (direction) of this plan (cached, host only).
 bool variant_fits(const dd_plan *p, int direction, const Variant &v);
 int32_t choose_variant(const dd_plan *p, int direction, int32_t in_type);
+// The variant a call uses: forced, else tuned, else the cost model's default.
+int32_t resolved_variant(const dd_plan *p, int direction, int32_t in_type);
 // Cost-model choice among `cand` (ids) that fit; -1 if none fits.
 int32_t best_by_model(const dd_plan *p, int direction, const int32_t *cand, int32_t n_cand);
-// The batch kernel's tile family (batch.hip) and the variant a plan uses in it.
-extern const int32_t kBatchFamily[];
-extern const int32_t kBatchFamilySize;
-int32_t batch_slot_of_variant(int32_t v);
-int32_t batch_variant(const dd_plan *p, int32_t in_type);
 // Time the candidates on the plan's own sizes (scratch buffers allocated
 // here); best id and mean ms.  Synchronises the stream.
 int tune_candidates(const dd_plan *p, int direction, int32_t in_type, int32_t reps, const int32_t *cand,

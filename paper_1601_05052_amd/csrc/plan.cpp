@@ -302,20 +302,6 @@ int32_t default_variant(const dd_plan *p, int direction, int32_t in_type) {
     return best_by_model(p, direction, all.data(), n);
 }
 
-int32_t batch_variant(const dd_plan *p, int32_t in_type) {
-    int32_t pick[2];
-    {
-        std::lock_guard<std::mutex> lock(p->mu);
-        pick[0] = p->tuned_batch[in_type];
-        pick[1] = p->forced[DD_FORWARD][in_type] >= 0 ? p->forced[DD_FORWARD][in_type]
-                                                       : p->tuned[DD_FORWARD][in_type];
-    }
-    for (int32_t id : pick)
-        if (id >= 0 && batch_slot_of_variant(id) >= 0 && variant_fits(p, DD_FORWARD, *find_variant(id)))
-            return id;
-    return best_by_model(p, DD_FORWARD, kBatchFamily, kBatchFamilySize);
-}
-
 int32_t choose_variant(const dd_plan *p, int direction, int32_t in_type) {
     std::lock_guard<std::mutex> lock(p->mu);
     if (p->forced[direction][in_type] >= 0)
@@ -323,6 +309,11 @@ int32_t choose_variant(const dd_plan *p, int direction, int32_t in_type) {
     if (p->tuned[direction][in_type] >= 0)
         return p->tuned[direction][in_type];
     return -2;  // caller computes the default outside the lock
+}
+
+int32_t resolved_variant(const dd_plan *p, int direction, int32_t in_type) {
+    const int32_t id = choose_variant(p, direction, in_type);
+    return id == -2 ? default_variant(p, direction, in_type) : id;
 }
 
 int make_args(const dd_plan *p, int direction, const Variant &v, const void *in, int64_t in_stride,

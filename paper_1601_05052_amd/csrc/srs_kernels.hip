@@ -12,6 +12,7 @@
 // (the data reuse of Sec. III-A, Eq. (3)).  Only binary32 additions; no MFMA.
 #include <hip/hip_runtime.h>
 
+#include "batch_desc.h"
 #include "internal.h"
 #include "srs_regwin.h"
 #include "srs_tile.h"
@@ -29,7 +30,7 @@ __global__ void __launch_bounds__(64 * NW)
     extern __shared__ float lds[];
     int32_t tile_t, tile_a;
     dev::tile_of_block(d, tile_t, tile_a);
-    dev::srs_tile_lds<TIn, IT, TDW, NW>(in, out, rel, base, d, tile_t, tile_a, lds);
+    dev::srs_tile_lds<TIn, IT, TDW, NW>(in, out, dev::as_ctab(rel), dev::as_ctab(base), d, tile_t, tile_a, lds);
 }
 
 template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX, bool FULL>
@@ -39,7 +40,8 @@ __global__ void __launch_bounds__(64 * NW)
     extern __shared__ __attribute__((aligned(16))) float lds_rw[];
     int32_t tile_t, tile_a;
     dev::tile_of_block(d, tile_t, tile_a);
-    dev::srs_tile_regwin<TIn, IT, TDW, NWR, NW, RPW, KMAX, FULL>(in, out, base, wrec, woff, d, tile_t, tile_a, lds_rw);
+    dev::srs_tile_regwin<TIn, IT, TDW, NWR, NW, RPW, KMAX, FULL>(in, out, dev::as_ctab(base), dev::as_ctab(wrec),
+                                                                 dev::as_ctab(woff), d, tile_t, tile_a, lds_rw);
 }
 
 template <typename TIn, int IT, int TDW, int NW, int RPW, int KMAX>
@@ -49,7 +51,8 @@ __global__ void __launch_bounds__(64 * NW)
     extern __shared__ __attribute__((aligned(16))) float lds_p[];
     int32_t tile_t, tile_a;
     dev::tile_of_block(d, tile_t, tile_a);
-    dev::srs_tile_ldsp<TIn, IT, TDW, NW, RPW, KMAX>(in, out, rel, base, d, tile_t, tile_a, lds_p);
+    dev::srs_tile_ldsp<TIn, IT, TDW, NW, RPW, KMAX>(in, out, dev::as_ctab(rel), dev::as_ctab(base), d, tile_t, tile_a,
+                                                    lds_p);
 }
 
 template <typename TIn, int IT, int NW, int U>
@@ -58,7 +61,106 @@ __global__ void __launch_bounds__(64 * NW)
                       const int32_t *__restrict__ base, SrsDims d) {
     int32_t tile_t, tile_a;
     dev::tile_of_block(d, tile_t, tile_a);
-    dev::srs_tile_direct<TIn, IT, NW, U>(in, out, rel, base, d, tile_t, tile_a);
+    dev::srs_tile_direct<TIn, IT, NW, U>(in, out, dev::as_ctab(rel), dev::as_ctab(base), d, tile_t, tile_a);
+}
+
+// Multi-beam forms: work-group g takes items[g] = (beam << 24) | logical tile
+// (the host lays the list out so each XCD walks contiguous runs of every
+// beam's tiles) and runs the same tile routine as the single-beam kernel.
+struct BeamTile {
+    const void *in;
+    float *out;
+    const BeamDesc *desc;
+    dev::ctab *rel, *base, *wrec, *woff;
+    SrsDims d;
+    int32_t tile_t, tile_a;
+};
+
+// Wave-uniform copies (the compiler cannot see that values read through a
+// dynamically indexed kernel argument are uniform; without this it wraps every
+// buffer load in a per-lane loop over the resource descriptor).
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(v >> 32));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+// Uniform pointer into global memory.  The round trip through a global
+// (address space 1) pointer lets the compiler treat loads through it as global
+// -- pointers read from memory are otherwise generic, and generic loads count
+// as divergent (they could address per-lane private memory).
+template <typename T>
+__device__ __forceinline__ T *uniform_ptr(T *p) {
+    typedef __attribute__((address_space(1))) T GT;
+    GT *g = (GT *)uniform64(reinterpret_cast<uintptr_t>(p));  // integer straight to a global pointer
+    return (T *)g;
+}
+
+__device__ __forceinline__ bool beam_tile(const BatchPtrs &ptrs, const BeamDesc *__restrict__ descs,
+                                          const uint32_t *__restrict__ items, BeamTile &bt) {
+    const uint32_t w = __builtin_amdgcn_readfirstlane(items[blockIdx.x]);
+    if (w == kNoItem)
+        return false;
+    const uint32_t beam = w >> 24, tile = w & 0xffffffu;
+    const BeamPtrs &bp = ptrs.b[beam];
+    bt.in = uniform_ptr(bp.in);
+    bt.out = uniform_ptr(bp.out);
+    bt.desc = uniform_ptr(&descs[beam]);
+    bt.d = bt.desc->d;
+    bt.rel = dev::as_ctab(bt.desc->rel);
+    bt.base = dev::as_ctab(bt.desc->base);
+    bt.wrec = dev::as_ctab(bt.desc->wrec);
+    bt.woff = dev::as_ctab(bt.desc->woff);
+    bt.d.in_stride = static_cast<int64_t>(uniform64(static_cast<uint64_t>(bp.in_stride)));
+    bt.d.out_stride = static_cast<int64_t>(uniform64(static_cast<uint64_t>(bp.out_stride)));
+    bt.tile_a = static_cast<int32_t>(tile % static_cast<uint32_t>(bt.d.n_acc_tiles));
+    bt.tile_t = static_cast<int32_t>(tile / static_cast<uint32_t>(bt.d.n_acc_tiles));
+    return true;
+}
+
+template <typename TIn, int IT, int TDW, int NW>
+__global__ void __launch_bounds__(64 * NW)
+    multi_lds_kernel(BatchPtrs ptrs, const BeamDesc *__restrict__ descs, const uint32_t *__restrict__ items) {
+    extern __shared__ float lds_ml[];
+    BeamTile bt;
+    if (!beam_tile(ptrs, descs, items, bt))
+        return;
+    dev::srs_tile_lds<TIn, IT, TDW, NW>(static_cast<const TIn *>(bt.in), bt.out, bt.rel, bt.base, bt.d,
+                                        bt.tile_t, bt.tile_a, lds_ml);
+}
+
+// OCC: waves per SIMD the multi-beam form must keep (1: no constraint); set
+// where the single-beam kernel sits exactly at a VGPR occupancy step.
+template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX, bool FULL, int OCC>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC)))
+    multi_regwin_kernel(BatchPtrs ptrs, const BeamDesc *__restrict__ descs, const uint32_t *__restrict__ items) {
+    extern __shared__ __attribute__((aligned(16))) float lds_mr[];
+    BeamTile bt;
+    if (!beam_tile(ptrs, descs, items, bt))
+        return;
+    dev::srs_tile_regwin<TIn, IT, TDW, NWR, NW, RPW, KMAX, FULL>(static_cast<const TIn *>(bt.in), bt.out,
+                                                                bt.base, bt.wrec, bt.woff, bt.d,
+                                                                bt.tile_t, bt.tile_a, lds_mr);
+}
+
+template <typename TIn, int IT, int TDW, int NW, int RPW, int KMAX>
+__global__ void __launch_bounds__(64 * NW)
+    multi_ldsp_kernel(BatchPtrs ptrs, const BeamDesc *__restrict__ descs, const uint32_t *__restrict__ items) {
+    extern __shared__ __attribute__((aligned(16))) float lds_mp[];
+    BeamTile bt;
+    if (!beam_tile(ptrs, descs, items, bt))
+        return;
+    dev::srs_tile_ldsp<TIn, IT, TDW, NW, RPW, KMAX>(static_cast<const TIn *>(bt.in), bt.out, bt.rel,
+                                                    bt.base, bt.d, bt.tile_t, bt.tile_a, lds_mp);
+}
+
+template <typename TIn, int IT, int NW, int U>
+__global__ void __launch_bounds__(64 * NW)
+    multi_direct_kernel(BatchPtrs ptrs, const BeamDesc *__restrict__ descs, const uint32_t *__restrict__ items) {
+    BeamTile bt;
+    if (!beam_tile(ptrs, descs, items, bt))
+        return;
+    dev::srs_tile_direct<TIn, IT, NW, U>(static_cast<const TIn *>(bt.in), bt.out, bt.rel, bt.base,
+                                         bt.d, bt.tile_t, bt.tile_a);
 }
 
 using LaunchFn = hipError_t (*)(const SrsArgs &, const SrsDims &, uint32_t, size_t, hipStream_t);
@@ -111,27 +213,41 @@ hipError_t launch_direct(const SrsArgs &a, const SrsDims &d, uint32_t blocks, si
 
 struct VariantImpl {
     Variant v;
-    LaunchFn fn[3];  // by input type: f32, f16, u8
+    LaunchFn fn[3];       // by input type: f32, f16, u8
+    const void *multi[3]; // multi-beam kernel, by input type
 };
+
+#define DD_FN(f) reinterpret_cast<const void *>(f)
 
 #define DD_LDS_VARIANT(ID, IT, TDW, NW, RATE)                                             \
     {{ID, IT, TDW, NW, KIND_LDS, 0, 0, 0, RATE},                                                \
-     {launch_lds<float, IT, TDW, NW>, launch_lds<_Float16, IT, TDW, NW>, launch_lds<uint8_t, IT, TDW, NW>}}
+     {launch_lds<float, IT, TDW, NW>, launch_lds<_Float16, IT, TDW, NW>, launch_lds<uint8_t, IT, TDW, NW>},    \
+     {DD_FN((multi_lds_kernel<float, IT, TDW, NW>)), DD_FN((multi_lds_kernel<_Float16, IT, TDW, NW>)),       \
+      DD_FN((multi_lds_kernel<uint8_t, IT, TDW, NW>))}}
 
 #define DD_LDSP_VARIANT(ID, IT, TDW, NW, RPW, KMAX, RATE)                                        \
     {{ID, IT, TDW, NW, KIND_LDS, RPW, 0, KMAX, RATE},                                                   \
      {launch_ldsp<float, IT, TDW, NW, RPW, KMAX>, launch_ldsp<_Float16, IT, TDW, NW, RPW, KMAX>, \
-      launch_ldsp<uint8_t, IT, TDW, NW, RPW, KMAX>}}
+      launch_ldsp<uint8_t, IT, TDW, NW, RPW, KMAX>},                                                    \
+     {DD_FN((multi_ldsp_kernel<float, IT, TDW, NW, RPW, KMAX>)),                                          \
+      DD_FN((multi_ldsp_kernel<_Float16, IT, TDW, NW, RPW, KMAX>)),                                       \
+      DD_FN((multi_ldsp_kernel<uint8_t, IT, TDW, NW, RPW, KMAX>))}}
 
 #define DD_DIRECT_VARIANT(ID, IT, NW, U, RATE)                                                            \
     {{ID, IT, 1, NW, KIND_DIRECT, U, 0, 0, RATE},                                                              \
-     {launch_direct<float, IT, NW, U>, launch_direct<_Float16, IT, NW, U>, launch_direct<uint8_t, IT, NW, U>}}
+     {launch_direct<float, IT, NW, U>, launch_direct<_Float16, IT, NW, U>, launch_direct<uint8_t, IT, NW, U>}, \
+     {DD_FN((multi_direct_kernel<float, IT, NW, U>)), DD_FN((multi_direct_kernel<_Float16, IT, NW, U>)),      \
+      DD_FN((multi_direct_kernel<uint8_t, IT, NW, U>))}}
 
-#define DD_RW_VARIANT(ID, IT, TDW, NWR, NW, RPW, KMAX, FULL, RATE)                                    \
+#define DD_RW_VARIANT(ID, IT, TDW, NWR, NW, RPW, KMAX, FULL, RATE) DD_RW_VARIANT_OCC(ID, IT, TDW, NWR, NW, RPW, KMAX, FULL, 1, RATE)
+#define DD_RW_VARIANT_OCC(ID, IT, TDW, NWR, NW, RPW, KMAX, FULL, OCC, RATE)                                    \
     {{ID, IT, TDW, NW, KIND_REGWIN, RPW, NWR, KMAX, RATE},                                               \
      {launch_regwin<float, IT, TDW, NWR, NW, RPW, KMAX, FULL>,                                           \
       launch_regwin<_Float16, IT, TDW, NWR, NW, RPW, KMAX, FULL>,                                        \
-      launch_regwin<uint8_t, IT, TDW, NWR, NW, RPW, KMAX, FULL>}}
+      launch_regwin<uint8_t, IT, TDW, NWR, NW, RPW, KMAX, FULL>},                                        \
+     {DD_FN((multi_regwin_kernel<float, IT, TDW, NWR, NW, RPW, KMAX, FULL, OCC>)),                       \
+      DD_FN((multi_regwin_kernel<_Float16, IT, TDW, NWR, NW, RPW, KMAX, FULL, OCC>)),                    \
+      DD_FN((multi_regwin_kernel<uint8_t, IT, TDW, NWR, NW, RPW, KMAX, FULL, OCC>))}}
 
 const VariantImpl kImpls[] = {
     DD_LDS_VARIANT(0, 4, 8, 4, 5.4f),   // 256 samples x 32 rows
@@ -165,7 +281,7 @@ const VariantImpl kImpls[] = {
     DD_DIRECT_VARIANT(28, 8, 4, 2, 7.3f),             // 512 x 4
     DD_RW_VARIANT(29, 8, 4, 44, 4, 1, 12, false, 17.5f),   // 512 x 16, wide window (adjoint)
     DD_RW_VARIANT(30, 8, 8, 76, 4, 1, 12, false, 20.8f),   // 512 x 32, wide window (adjoint)
-    DD_RW_VARIANT(31, 8, 8, 40, 8, 1, 12, false, 20.0f),   // 512 x 64, eight waves, short staging
+    DD_RW_VARIANT_OCC(31, 8, 8, 40, 8, 1, 12, false, 4, 20.0f),  // 512 x 64, eight waves, short staging
     DD_RW_VARIANT(32, 16, 4, 48, 4, 1, 20, false, 18.0f),  // 1024 x 16, short staging
 };
 constexpr int32_t kNumImpls = sizeof(kImpls) / sizeof(kImpls[0]);
@@ -203,6 +319,8 @@ int32_t max_lds_bytes() {
     }
     return cached;
 }
+
+const void *multi_kernel(const Variant &v, int32_t in_type) { return kImpls[v.id].multi[in_type]; }
 
 hipError_t launch_srs(const Variant &v, int32_t in_type, const SrsArgs &a, hipStream_t stream) {
     const VariantImpl &impl = kImpls[v.id];

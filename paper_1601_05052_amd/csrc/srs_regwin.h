@@ -85,9 +85,8 @@ __device__ __forceinline__ uint32_t lds_address(const float *p) {
 
 template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX, bool FULL>
 __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, float *__restrict__ out,
-                                                const int32_t *__restrict__ base,
-                                                const int32_t *__restrict__ wrec,
-                                                const int32_t *__restrict__ woff, const SrsDims &d,
+                                                ctab *__restrict__ base, ctab *__restrict__ wrec,
+                                                ctab *__restrict__ woff, const SrsDims &d,
                                                 int32_t tile_t, int32_t tile_a, float *lds) {
     using RW = RegWin<IT, TDW, NWR>;
     constexpr int TT = 64 * IT;
@@ -96,9 +95,9 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t t0 = static_cast<int64_t>(tile_t) * TT;
-    const int32_t *base_tile = base + static_cast<int64_t>(tile_a) * d.n_rows;
-    const int32_t *wrec_tile = wrec + static_cast<int64_t>(tile_a) * d.n_rows * NW + wave;
-    const int32_t *woff_tile = woff + (static_cast<int64_t>(tile_a) * d.n_rows * NW + wave) * TDW;
+    ctab *base_tile = base + static_cast<int64_t>(tile_a) * d.n_rows;
+    ctab *wrec_tile = wrec + static_cast<int64_t>(tile_a) * d.n_rows * NW + wave;
+    ctab *woff_tile = woff + (static_cast<int64_t>(tile_a) * d.n_rows * NW + wave) * TDW;
     const int32_t nk = d.wcap >> 6;  // wcap is a multiple of 64
 
     typename RW::Acc acc;
@@ -216,8 +215,7 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
 // operand from LDS at a wave-uniform offset, 64 consecutive words per read).
 template <typename TIn, int IT, int TDW, int NW, int RPW, int KMAX>
 __device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float *__restrict__ out,
-                                              const int32_t *__restrict__ rel,
-                                              const int32_t *__restrict__ base, const SrsDims &d,
+                                              ctab *__restrict__ rel, ctab *__restrict__ base, const SrsDims &d,
                                               int32_t tile_t, int32_t tile_a, float *lds) {
     constexpr int TT = 64 * IT;
     constexpr int TA = TDW * NW;
@@ -225,8 +223,8 @@ __device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t t0 = static_cast<int64_t>(tile_t) * TT;
-    const int32_t *base_tile = base + static_cast<int64_t>(tile_a) * d.n_rows;
-    const int32_t *rel_tile = rel + static_cast<int64_t>(tile_a) * d.n_rows * TA + wave * TDW;
+    ctab *base_tile = base + static_cast<int64_t>(tile_a) * d.n_rows;
+    ctab *rel_tile = rel + static_cast<int64_t>(tile_a) * d.n_rows * TA + wave * TDW;
     const int32_t nk = d.wcap >> 6;
     const int32_t buf_dw = CR * d.wcap;
 
@@ -271,7 +269,7 @@ __device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float 
         const int32_t nr = min(CR, d.n_rows - r0);
         const float *buf = lds + (c & 1) * buf_dw + lane;
         for (int32_t rr = 0; rr < nr; ++rr) {
-            const int32_t *o = rel_tile + static_cast<int64_t>(r0 + rr) * TA;
+            ctab *o = rel_tile + static_cast<int64_t>(r0 + rr) * TA;
             const float *row = buf + rr * d.wcap;
 #pragma unroll
             for (int k = 0; k < TDW; ++k) {
@@ -311,15 +309,14 @@ __device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float 
 // loads (lane l: samples t0 + l + 64j, coalesced), U input rows in flight.
 template <typename TIn, int IT, int NW, int U>
 __device__ __forceinline__ void srs_tile_direct(const TIn *__restrict__ in, float *__restrict__ out,
-                                                const int32_t *__restrict__ rel,
-                                                const int32_t *__restrict__ base, const SrsDims &d,
+                                                ctab *__restrict__ rel, ctab *__restrict__ base, const SrsDims &d,
                                                 int32_t tile_t, int32_t tile_a) {
     constexpr int TT = 64 * IT;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t t0 = static_cast<int64_t>(tile_t) * TT;
-    const int32_t *base_tile = base + static_cast<int64_t>(tile_a) * d.n_rows;
-    const int32_t *rel_tile = rel + static_cast<int64_t>(tile_a) * d.n_rows * NW + wave;
+    ctab *base_tile = base + static_cast<int64_t>(tile_a) * d.n_rows;
+    ctab *rel_tile = rel + static_cast<int64_t>(tile_a) * d.n_rows * NW + wave;
     const int32_t n_bytes = static_cast<int32_t>(d.in_valid * static_cast<int64_t>(sizeof(TIn)));
     float acc[IT];
 #pragma unroll

@@ -21,6 +21,12 @@ __device__ __forceinline__ float to_f32<_Float16>(_Float16 v) { return static_ca
 template <>
 __device__ __forceinline__ float to_f32<uint8_t>(uint8_t v) { return static_cast<float>(v); }
 
+// Tile tables are read-only for the whole launch: reading them through the
+// constant address space lets the compiler use scalar loads for wave-uniform
+// indices, also when the table pointer itself was read from memory.
+typedef const __attribute__((address_space(4))) int32_t ctab;
+__device__ __forceinline__ ctab *as_ctab(const int32_t *p) { return (ctab *)reinterpret_cast<uintptr_t>(p); }
+
 struct SrsDims {
     int64_t in_stride;
     int64_t in_valid;
@@ -56,16 +62,15 @@ __device__ __forceinline__ void tile_of_block(const SrsDims &d, int32_t &tile_t,
 // 64 lanes read 64 consecutive LDS words (conflict-free).
 template <typename TIn, int IT, int TDW, int NW>
 __device__ __forceinline__ void srs_tile_lds(const TIn *__restrict__ in, float *__restrict__ out,
-                                             const int32_t *__restrict__ rel,
-                                             const int32_t *__restrict__ base, const SrsDims &d,
+                                             ctab *__restrict__ rel, ctab *__restrict__ base, const SrsDims &d,
                                              int32_t tile_t, int32_t tile_a, float *lds) {
     constexpr int TT = 64 * IT;
     constexpr int TA = TDW * NW;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t t0 = static_cast<int64_t>(tile_t) * TT;
-    const int32_t *rel_tile = rel + static_cast<int64_t>(tile_a) * d.n_rows * TA + wave * TDW;
-    const int32_t *base_tile = base + static_cast<int64_t>(tile_a) * d.n_rows;
+    ctab *rel_tile = rel + static_cast<int64_t>(tile_a) * d.n_rows * TA + wave * TDW;
+    ctab *base_tile = base + static_cast<int64_t>(tile_a) * d.n_rows;
 
     float acc[TDW][IT];
 #pragma unroll
@@ -93,7 +98,7 @@ __device__ __forceinline__ void srs_tile_lds(const TIn *__restrict__ in, float *
         }
         __syncthreads();  // window staged
         for (int32_t rr = 0; rr < nr; ++rr) {
-            const int32_t *o = rel_tile + static_cast<int64_t>(r0 + rr) * TA;
+            ctab *o = rel_tile + static_cast<int64_t>(r0 + rr) * TA;
             const float *row = lds + rr * d.wcap + lane;
 #pragma unroll
             for (int k = 0; k < TDW; ++k) {

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <map>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -149,33 +150,64 @@ static int check_tune_args(const dd_plan *p, int direction, int in_type, int32_t
     return DD_OK;
 }
 
+namespace {
+
+// Tune one (plan, direction, dtype): the cache file first, then `memo` (plans
+// of the same shape tuned earlier in this call), else time every variant.
+int tune_one(dd_plan *p, int direction, int32_t in_type, int32_t reps, const char *cache_path, hipStream_t stream,
+             std::map<std::string, std::pair<int32_t, float>> *memo, int32_t *best_out, float *ms_out) {
+    const std::string key = cache_key(p, direction, in_type);
+    int32_t best = -1;
+    float best_t = 0.f;
+    bool have = false;
+    if (memo) {
+        auto it = memo->find(key);
+        if (it != memo->end()) {
+            best = it->second.first;
+            best_t = it->second.second;
+            have = true;
+        }
+    }
+    if (!have && cache_path && cache_lookup(cache_path, key, &best, &best_t) &&
+        variant_fits(p, direction, *find_variant(best)))
+        have = true;
+    if (!have) {
+        int32_t n = 0;
+        variants(&n);
+        std::vector<int32_t> all(n);
+        for (int32_t i = 0; i < n; ++i)
+            all[i] = i;
+        int rc = tune_candidates(p, direction, in_type, reps, all.data(), n, stream, &best, &best_t);
+        if (rc != DD_OK)
+            return rc;
+        if (cache_path)
+            cache_store(cache_path, key, best, best_t);
+    }
+    if (memo)
+        (*memo)[key] = std::make_pair(best, best_t);
+    {
+        std::lock_guard<std::mutex> lock(p->mu);
+        p->tuned[direction][in_type] = best;
+    }
+    *best_out = best;
+    *ms_out = best_t;
+    return DD_OK;
+}
+
+}  // namespace
+
 extern "C" int dd_autotune(dd_plan *p, dd_direction direction, dd_dtype in_type, int32_t reps,
                            const char *cache_path, void *stream_v, int32_t *best_variant, float *best_ms) {
     clear_error();
     int rc = check_tune_args(p, direction, in_type, reps);
     if (rc != DD_OK)
         return rc;
-    hipStream_t stream = static_cast<hipStream_t>(stream_v);
-    const std::string key = cache_key(p, direction, in_type);
     int32_t best = -1;
     float best_t = 0.f;
-    if (!(cache_path && cache_lookup(cache_path, key, &best, &best_t) &&
-          variant_fits(p, direction, *find_variant(best)))) {
-        int32_t n = 0;
-        variants(&n);
-        std::vector<int32_t> all(n);
-        for (int32_t i = 0; i < n; ++i)
-            all[i] = i;
-        rc = tune_candidates(p, direction, in_type, reps, all.data(), n, stream, &best, &best_t);
-        if (rc != DD_OK)
-            return rc;
-        if (cache_path)
-            cache_store(cache_path, key, best, best_t);
-    }
-    {
-        std::lock_guard<std::mutex> lock(p->mu);
-        p->tuned[direction][in_type] = best;
-    }
+    rc = tune_one(p, direction, in_type, reps, cache_path, static_cast<hipStream_t>(stream_v), nullptr, &best,
+                  &best_t);
+    if (rc != DD_OK)
+        return rc;
     if (best_variant)
         *best_variant = best;
     if (best_ms)
@@ -188,25 +220,19 @@ extern "C" int dd_batch_autotune(dd_plan *const *plans, int32_t n_beams, dd_dtyp
     clear_error();
     if (!plans || n_beams < 1)
         return fail(DD_EINVAL, "plans is NULL or n_beams < 1");
-    hipStream_t stream = static_cast<hipStream_t>(stream_v);
     for (int32_t b = 0; b < n_beams; ++b) {
-        dd_plan *p = plans[b];
-        int rc = check_tune_args(p, DD_FORWARD, in_type, reps);
+        int rc = check_tune_args(plans[b], DD_FORWARD, in_type, reps);
         if (rc != DD_OK)
             return rc;
-        const std::string key = cache_key(p, DD_FORWARD, in_type) + "|batch";
+    }
+    std::map<std::string, std::pair<int32_t, float>> memo;
+    for (int32_t b = 0; b < n_beams; ++b) {
         int32_t best = -1;
         float best_t = 0.f;
-        if (!(cache_path && cache_lookup(cache_path, key, &best, &best_t) && batch_slot_of_variant(best) >= 0 &&
-              variant_fits(p, DD_FORWARD, *find_variant(best)))) {
-            rc = tune_candidates(p, DD_FORWARD, in_type, reps, kBatchFamily, kBatchFamilySize, stream, &best, &best_t);
-            if (rc != DD_OK)
-                return rc;
-            if (cache_path)
-                cache_store(cache_path, key, best, best_t);
-        }
-        std::lock_guard<std::mutex> lock(p->mu);
-        p->tuned_batch[in_type] = best;
+        int rc = tune_one(plans[b], DD_FORWARD, in_type, reps, cache_path, static_cast<hipStream_t>(stream_v), &memo,
+                          &best, &best_t);
+        if (rc != DD_OK)
+            return rc;
     }
     return DD_OK;
 }

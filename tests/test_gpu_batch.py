@@ -1,11 +1,12 @@
-"""Batched persistent launch: every beam equals the oracle and its own
-single-beam run; graph replays pick up new inputs and pointers."""
+"""Batched graph launch: every beam equals the oracle and, bit for bit, its
+own single-beam run (same tile variant, same summation order); graph replays
+pick up new inputs and pointers."""
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from paper_1601_05052_amd import DD_F16, DD_F32, DD_U8, Batch, Plan, dedisperse
+from paper_1601_05052_amd import DD_F16, DD_F32, DD_U8, Batch, DedispError, Plan, dedisperse, tile_variants
 from tests import gates
 from tests.gpu_util import sample_points, to_dev, to_host, torch_mod
 
@@ -36,6 +37,7 @@ def test_batch_matches_oracle_and_single_beam(dtype, code):
         xs_h.append(x)
     xs = [to_dev(x) for x in xs_h]
     batch = Batch(plans, dtype=code)
+    assert batch.variants() == [p.get_tile(dtype=code) for p in plans]
     outs = batch.run(xs)
     for b, p, x, y in zip(beams, plans, xs_h, outs):
         table = oracle.delay_table(*b.plan_args()[:7])
@@ -47,12 +49,30 @@ def test_batch_matches_oracle_and_single_beam(dtype, code):
             absref = oracle.dedisperse(np.abs(x.astype(np.float64)), table, b.n_samples)
             gates.gate(yh, ref, absref, what=b.name)
         single = to_host(dedisperse(to_dev(x), p))
-        if p.get_tile(dtype=code) in batch_family():
-            assert np.array_equal(single, yh), b.name
+        assert np.array_equal(single, yh), b.name
 
 
-def batch_family():
-    return {17, 19, 14, 21, 20, 24, 25, 7}
+def test_batch_mixed_forced_variants_exact():
+    """Beams forced onto different kinds (register window, LDS, prefetched
+    LDS, direct) run as separate groups of one graph; each is exact."""
+    beams = small_beams()[:5]
+    plans = [Plan.from_setup(b) for b in beams]
+    kinds = {v[0]: v[4] for v in tile_variants()}
+    wanted = [17, 21, 27, 9, 19]
+    for p, v in zip(plans, wanted):
+        try:
+            p.set_tile(v)
+        except DedispError:
+            pass  # variant does not fit this beam: keep the automatic choice
+    batch = Batch(plans)
+    got = batch.variants()
+    assert got == [p.get_tile() for p in plans]
+    assert len({kinds[v] for v in got}) >= 2
+    xs_h = [synth.integers_f32(b.n_channels, p.input_samples, seed=50 + i) for i, (b, p) in enumerate(zip(beams, plans))]
+    outs = batch.run([to_dev(x) for x in xs_h])
+    for b, x, y in zip(beams, xs_h, outs):
+        table = oracle.delay_table(*b.plan_args()[:7])
+        gates.exact(to_host(y), oracle.dedisperse(x, table, b.n_samples), what=b.name)
 
 
 def test_batch_replay_new_data_and_pointers():
@@ -92,14 +112,15 @@ def test_batched_workload_sampled_u8():
         gates.exact(yh, oracle.dedisperse_points(x, table, i, t), what=b.name)
 
 
-def test_batch_autotune_chooses_family_variants_and_stays_exact():
-    """Per-beam tuning (dd_batch_autotune) picks tiles from the batch kernel's
-    family, and the tuned batch still reproduces the oracle bit for bit on
-    integer data."""
+def test_batch_autotune_uses_tuned_tiles_and_stays_exact():
+    """Per-beam tuning (dd_batch_autotune) stores each plan's fastest tile;
+    the batch runs with exactly those tiles and still reproduces the oracle
+    bit for bit on integer data."""
     torch = torch_mod()
     beams = small_beams()[:5]
     plans = [Plan.from_setup(b) for b in beams]
     batch = Batch(plans, tune=True, reps=1)
+    assert batch.variants() == [p.get_tile() for p in plans]
     xs_h = [synth.integers_f32(b.n_channels, p.input_samples, seed=70 + i) for i, (b, p) in enumerate(zip(beams, plans))]
     outs = batch.run([to_dev(x) for x in xs_h])
     torch.cuda.synchronize()

@@ -188,3 +188,16 @@ def test_generated_asm_header_is_current():
     spec.loader.exec_module(mod)
     with open(os.path.join(ROOT, "paper_1601_05052_amd", "csrc", "regwin_asm.h")) as f:
         assert f.read() == mod.render()
+
+
+def test_one_hip_runtime_in_process():
+    """libdedisp binds to the HIP runtime PyTorch loaded (one libamdhip64 and
+    one HSA runtime mapped), so torch streams are valid library handles."""
+    _lib.lib()
+    import torch  # noqa: F401
+    with open("/proc/self/maps") as f:
+        maps = f.read().splitlines()
+    hip = {l.split()[-1] for l in maps if "libamdhip64" in l}
+    hsa = {l.split()[-1] for l in maps if "libhsa-runtime64" in l}
+    assert len(hip) == 1, hip
+    assert len(hsa) == 1, hsa
