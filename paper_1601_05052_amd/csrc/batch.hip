@@ -153,8 +153,7 @@ extern "C" int dd_batch_create(dd_batch **out, const dd_plan *const *plans, int3
         std::memset(&bd, 0, sizeof(bd));
         bd.rel = a.rel;
         bd.base = a.base;
-        bd.wrec = a.wrec;
-        bd.woff = a.woff;
+        bd.recs = a.recs;
         bd.d.in_valid = a.in_valid;
         bd.d.n_t = a.n_t;
         bd.d.n_acc = a.n_acc;

@@ -32,8 +32,7 @@ struct BatchPtrs {
 struct BeamDesc {
     const int32_t *rel;
     const int32_t *base;
-    const int32_t *wrec;
-    const int32_t *woff;
+    const int32_t *recs;
     dev::SrsDims d;  // in_stride / out_stride are taken from BeamPtrs
 };
 

@@ -24,8 +24,10 @@ S*l + c (c a multiple of S) has its q-th quad at physical
 offsets.
 
 Only the quads a row needs are loaded: the first S unconditionally, the rest
-behind a compare-and-branch on the row's quad count.  Accumulators are pinned
-with explicit-register constraints; window registers are clobbered.
+behind a compare-and-branch on the row's quad count.  Accumulators and the
+window are pinned with explicit-register constraints; the window is the
+output of load() and an input of add(), so scalar work can be placed between
+the LDS wait and the additions.
 
     python gen_regwin_asm.py      # rewrites regwin_asm.h next to this file
 """
@@ -143,31 +145,44 @@ def gen_config(it, tdw, nwr, acc0):
         return cl
 
     o_ins = ['[o%d] "s"(o[%d])' % (a, a) for a in range(tdw)]
-    wa = list(range(w0, w0 + nwr))
+    win_parts = split(nwr)
 
-    # One input row: load nq window quads from LDS address `addr`, then add.
+    # Window registers as values: load() defines them, add() reads them, so
+    # scalar work can sit between the two (e.g. the next chunk's records).
+    L.append("    struct Win {")
+    for k, n in enumerate(win_parts):
+        L.append("        %s p%d;" % (vec_type(n), k))
+    L.append("    };")
+    w_outs, w_ins = [], []
+    reg = w0
+    for k, n in enumerate(win_parts):
+        rng = "v[%d:%d]" % (reg, reg + n - 1) if n > 1 else "v%d" % reg
+        w_outs.append('"=&{%s}"(w.p%d)' % (rng, k))
+        w_ins.append('"{%s}"(w.p%d)' % (rng, k))
+        reg += n
+
+    # Load nq window quads from LDS byte address `addr` and wait for them; dep
+    # is an SGPR set to 0 after the wait (a data dependence that keeps later
+    # scalar loads from being scheduled above it).
     L.append("    // addr: LDS byte address of this lane's first window quad; nq: quads to")
-    L.append("    // load (NQ_MIN <= nq <= NQ_MAX); o: per-accumulator-row window offsets.")
-    L.append("    __device__ static __forceinline__ void row(Acc &a, uint32_t addr, int nq, const int (&o)[%d]) {" % tdw)
+    L.append("    // load (NQ_MIN <= nq <= NQ_MAX).  Quads past nq are left undefined.")
+    L.append("    __device__ static __forceinline__ void load(Win &w, uint32_t addr, int nq, int &dep) {")
     L.append("        asm volatile(")
     L.extend(loads(w0, "addr", "nq"))
     L.append('            "s_waitcnt lgkmcnt(0)\\n\\t"')
-    L.extend(adds(w0))
-    L.append("            : " + ", ".join(outs))
-    L.append("            : " + ", ".join(['[addr] "v"(addr)', '[nq] "s"(nq)'] + o_ins))
-    L.extend(clobbers(wa))
+    L.append('            "s_mov_b32 %[dep], 0\\n\\t"')
+    L.append("            : " + ", ".join(w_outs + ['[dep] "=s"(dep)']))
+    L.append("            : " + ", ".join(['[addr] "v"(addr)', '[nq] "s"(nq)']))
+    L.append('            : "scc", "memory");')
     L.append("    }")
-    # Same, loading the whole window (no branches).
-    L.append("    __device__ static __forceinline__ void row_full(Acc &a, uint32_t addr, const int (&o)[%d]) {" % tdw)
+    # Add the window at every accumulator row's offset o[a].
+    L.append("    // o: per-accumulator-row window offsets, 0 <= o[a] <= NWR - IT.")
+    L.append("    __device__ static __forceinline__ void add(Acc &a, const Win &w, const int (&o)[%d]) {" % tdw)
     L.append("        asm volatile(")
-    for q in range(nq_max):
-        L.append('            "ds_read_b128 v[%d:%d], %%[addr] offset:%d\\n\\t"'
-                 % (w0 + 4 * q, w0 + 4 * q + 3, 16 * quad_offset(q, s)))
-    L.append('            "s_waitcnt lgkmcnt(0)\\n\\t"')
     L.extend(adds(w0))
     L.append("            : " + ", ".join(outs))
-    L.append("            : " + ", ".join(['[addr] "v"(addr)'] + o_ins))
-    L.extend(clobbers(wa))
+    L.append("            : " + ", ".join(w_ins + o_ins))
+    L.append('            : "scc", "m0");')
     L.append("    }")
     L.append("};")
     return "\n".join(L)

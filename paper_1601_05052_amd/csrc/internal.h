@@ -70,8 +70,7 @@ struct SrsArgs {
     int32_t n_rows;
     const int32_t *rel;    // LDS kind: [n_tiles][n_rows][TA] offsets relative to base
     const int32_t *base;   // [n_tiles][n_rows] staged-row start relative to the tile's first sample
-    const int32_t *wrec;   // regwin: [n_tiles][n_rows][waves] lane-window start in the staged row
-    const int32_t *woff;   // regwin: [n_tiles][n_rows][waves][items_acc] offsets in the lane window
+    const int32_t *recs;   // regwin: [n_tiles][waves][n_chunks * rows per chunk][1 + items_acc/4] window records
     int32_t wcap;          // samples per staged row
     int32_t rows_per_chunk;
     int32_t lds_bytes;     // dynamic LDS per work-group
@@ -94,7 +93,7 @@ struct Layout {
     int32_t rows_per_chunk = 0;
     int32_t lds_bytes = 0;
     int32_t max_spread = 0;
-    std::vector<int32_t> base, rel, wrec, woff;
+    std::vector<int32_t> base, rel, recs;
 };
 
 // Device copy of a Layout's tables.
@@ -105,8 +104,7 @@ struct TileTables {
     int32_t lds_bytes = 0;
     int32_t *d_base = nullptr;
     int32_t *d_rel = nullptr;
-    int32_t *d_wrec = nullptr;
-    int32_t *d_woff = nullptr;
+    int32_t *d_recs = nullptr;
 };
 
 int32_t max_lds_bytes();

@@ -63,6 +63,14 @@ static inline int32_t offset_of(const dd_plan *p, int direction, int32_t r, int3
     return direction == DD_FORWARD ? p->delay[(int64_t)a * p->C + r] : -p->delay[(int64_t)r * p->C + a];
 }
 
+// Register-window records: dwords per (row, wave) and rows per table (padded
+// to whole chunks of waves * rpw rows).
+static int32_t regwin_rd(const Variant &v) { return 1 + v.items_acc / 4; }
+static int64_t regwin_rows(const Variant &v, int32_t rows) {
+    const int64_t cr = (int64_t)v.waves * v.rpw;
+    return (rows + cr - 1) / cr * cr;
+}
+
 void compute_layout(const dd_plan *p, int direction, const Variant &v, bool build, Layout *L) {
     const int32_t R = direction == DD_FORWARD ? p->C : p->D;
     const int32_t A = direction == DD_FORWARD ? p->D : p->C;
@@ -74,10 +82,8 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
         L->base.resize((size_t)n_tiles * R);
         if (v.kind != KIND_REGWIN)
             L->rel.resize((size_t)n_tiles * R * TA);
-        else {
-            L->wrec.resize((size_t)n_tiles * R * v.waves);
-            L->woff.resize((size_t)n_tiles * R * TA);
-        }
+        else  // rows padded to whole chunks; padding records stay zero
+            L->recs.assign((size_t)n_tiles * v.waves * regwin_rows(v, R) * regwin_rd(v), 0);
     }
     int32_t max_spread = 0;
     int64_t need = 0;  // regwin: largest staged-row index a lane window touches, + 1
@@ -119,10 +125,14 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
                 if (build) {
                     const int32_t c = ws / 4;
                     const int32_t u_bytes = 16 * (S == 1 ? c : c + c / S);  // padded LDS layout
-                    L->wrec[((size_t)k * R + r) * v.waves + w] = u_bytes | (nq << 20);
-                    for (int32_t j = 0; j < TDW; ++j)
-                        L->woff[(((size_t)k * R + r) * v.waves + w) * TDW + j] =
-                            offset_of(p, direction, r, std::min(A - 1, k * TA + w * TDW + j)) - lo - ws;
+                    const int32_t RD = regwin_rd(v);
+                    int32_t *rec = &L->recs[(((size_t)k * v.waves + w) * regwin_rows(v, R) + r) * RD];
+                    rec[0] = u_bytes | (nq << 20);
+                    for (int32_t j = 0; j < TDW; ++j) {
+                        const uint32_t o = (uint32_t)(offset_of(p, direction, r, std::min(A - 1, k * TA + w * TDW + j)) -
+                                                      lo - ws);  // 0 <= o <= nwr - items_t < 256
+                        rec[1 + j / 4] = (int32_t)((uint32_t)rec[1 + j / 4] | (o << (8 * (j % 4))));
+                    }
                 }
             }
         }
@@ -202,8 +212,7 @@ static int upload(const std::vector<int32_t> &h, int32_t **d) {
 static void free_tables(TileTables &t) {
     (void)hipFree(t.d_base);
     (void)hipFree(t.d_rel);
-    (void)hipFree(t.d_wrec);
-    (void)hipFree(t.d_woff);
+    (void)hipFree(t.d_recs);
     t = TileTables();
 }
 
@@ -238,9 +247,7 @@ int plan_tables(const dd_plan *p, int direction, const Variant &v, const TileTab
     if (rc == DD_OK)
         rc = upload(L.rel, &t.d_rel);
     if (rc == DD_OK)
-        rc = upload(L.wrec, &t.d_wrec);
-    if (rc == DD_OK)
-        rc = upload(L.woff, &t.d_woff);
+        rc = upload(L.recs, &t.d_recs);
     if (rc != DD_OK) {
         free_tables(t);
         return rc;
@@ -339,8 +346,7 @@ int make_args(const dd_plan *p, int direction, const Variant &v, const void *in,
     }
     a->rel = t->d_rel;
     a->base = t->d_base;
-    a->wrec = t->d_wrec;
-    a->woff = t->d_woff;
+    a->recs = t->d_recs;
     a->wcap = t->wcap;
     a->rows_per_chunk = t->rows_per_chunk;
     a->lds_bytes = t->lds_bytes;

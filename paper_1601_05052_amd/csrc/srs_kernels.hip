@@ -33,15 +33,15 @@ __global__ void __launch_bounds__(64 * NW)
     dev::srs_tile_lds<TIn, IT, TDW, NW>(in, out, dev::as_ctab(rel), dev::as_ctab(base), d, tile_t, tile_a, lds);
 }
 
-template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX, bool FULL>
+template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX>
 __global__ void __launch_bounds__(64 * NW)
     srs_regwin_kernel(const TIn *__restrict__ in, float *__restrict__ out, const int32_t *__restrict__ base,
-                      const int32_t *__restrict__ wrec, const int32_t *__restrict__ woff, SrsDims d) {
+                      const int32_t *__restrict__ recs, SrsDims d) {
     extern __shared__ __attribute__((aligned(16))) float lds_rw[];
     int32_t tile_t, tile_a;
     dev::tile_of_block(d, tile_t, tile_a);
-    dev::srs_tile_regwin<TIn, IT, TDW, NWR, NW, RPW, KMAX, FULL>(in, out, dev::as_ctab(base), dev::as_ctab(wrec),
-                                                                 dev::as_ctab(woff), d, tile_t, tile_a, lds_rw);
+    dev::srs_tile_regwin<TIn, IT, TDW, NWR, NW, RPW, KMAX>(in, out, dev::as_ctab(base), dev::as_ctab(recs), d,
+                                                           tile_t, tile_a, lds_rw);
 }
 
 template <typename TIn, int IT, int TDW, int NW, int RPW, int KMAX>
@@ -71,7 +71,7 @@ struct BeamTile {
     const void *in;
     float *out;
     const BeamDesc *desc;
-    dev::ctab *rel, *base, *wrec, *woff;
+    dev::ctab *rel, *base, *recs;
     SrsDims d;
     int32_t tile_t, tile_a;
 };
@@ -108,8 +108,7 @@ __device__ __forceinline__ bool beam_tile(const BatchPtrs &ptrs, const BeamDesc 
     bt.d = bt.desc->d;
     bt.rel = dev::as_ctab(bt.desc->rel);
     bt.base = dev::as_ctab(bt.desc->base);
-    bt.wrec = dev::as_ctab(bt.desc->wrec);
-    bt.woff = dev::as_ctab(bt.desc->woff);
+    bt.recs = dev::as_ctab(bt.desc->recs);
     bt.d.in_stride = static_cast<int64_t>(uniform64(static_cast<uint64_t>(bp.in_stride)));
     bt.d.out_stride = static_cast<int64_t>(uniform64(static_cast<uint64_t>(bp.out_stride)));
     bt.tile_a = static_cast<int32_t>(tile % static_cast<uint32_t>(bt.d.n_acc_tiles));
@@ -130,16 +129,15 @@ __global__ void __launch_bounds__(64 * NW)
 
 // OCC: waves per SIMD the multi-beam form must keep (1: no constraint); set
 // where the single-beam kernel sits exactly at a VGPR occupancy step.
-template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX, bool FULL, int OCC>
+template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX, int OCC>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC)))
     multi_regwin_kernel(BatchPtrs ptrs, const BeamDesc *__restrict__ descs, const uint32_t *__restrict__ items) {
     extern __shared__ __attribute__((aligned(16))) float lds_mr[];
     BeamTile bt;
     if (!beam_tile(ptrs, descs, items, bt))
         return;
-    dev::srs_tile_regwin<TIn, IT, TDW, NWR, NW, RPW, KMAX, FULL>(static_cast<const TIn *>(bt.in), bt.out,
-                                                                bt.base, bt.wrec, bt.woff, bt.d,
-                                                                bt.tile_t, bt.tile_a, lds_mr);
+    dev::srs_tile_regwin<TIn, IT, TDW, NWR, NW, RPW, KMAX>(static_cast<const TIn *>(bt.in), bt.out, bt.base, bt.recs, bt.d,
+                                                           bt.tile_t, bt.tile_a, lds_mr);
 }
 
 template <typename TIn, int IT, int TDW, int NW, int RPW, int KMAX>
@@ -182,14 +180,14 @@ hipError_t launch_lds(const SrsArgs &a, const SrsDims &d, uint32_t blocks, size_
     return hipGetLastError();
 }
 
-template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX, bool FULL>
+template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX>
 hipError_t launch_regwin(const SrsArgs &a, const SrsDims &d, uint32_t blocks, size_t lds, hipStream_t s) {
-    auto fn = srs_regwin_kernel<TIn, IT, TDW, NWR, NW, RPW, KMAX, FULL>;
+    auto fn = srs_regwin_kernel<TIn, IT, TDW, NWR, NW, RPW, KMAX>;
     hipError_t e = set_lds_limit(reinterpret_cast<const void *>(fn), lds);
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * NW), lds, s, static_cast<const TIn *>(a.in), a.out, a.base,
-                       a.wrec, a.woff, d);
+                       a.recs, d);
     return hipGetLastError();
 }
 
@@ -239,15 +237,15 @@ struct VariantImpl {
      {DD_FN((multi_direct_kernel<float, IT, NW, U>)), DD_FN((multi_direct_kernel<_Float16, IT, NW, U>)),      \
       DD_FN((multi_direct_kernel<uint8_t, IT, NW, U>))}}
 
-#define DD_RW_VARIANT(ID, IT, TDW, NWR, NW, RPW, KMAX, FULL, RATE) DD_RW_VARIANT_OCC(ID, IT, TDW, NWR, NW, RPW, KMAX, FULL, 1, RATE)
-#define DD_RW_VARIANT_OCC(ID, IT, TDW, NWR, NW, RPW, KMAX, FULL, OCC, RATE)                                    \
+#define DD_RW_VARIANT(ID, IT, TDW, NWR, NW, RPW, KMAX, RATE) DD_RW_VARIANT_OCC(ID, IT, TDW, NWR, NW, RPW, KMAX, 1, RATE)
+#define DD_RW_VARIANT_OCC(ID, IT, TDW, NWR, NW, RPW, KMAX, OCC, RATE)                                    \
     {{ID, IT, TDW, NW, KIND_REGWIN, RPW, NWR, KMAX, RATE},                                               \
-     {launch_regwin<float, IT, TDW, NWR, NW, RPW, KMAX, FULL>,                                           \
-      launch_regwin<_Float16, IT, TDW, NWR, NW, RPW, KMAX, FULL>,                                        \
-      launch_regwin<uint8_t, IT, TDW, NWR, NW, RPW, KMAX, FULL>},                                        \
-     {DD_FN((multi_regwin_kernel<float, IT, TDW, NWR, NW, RPW, KMAX, FULL, OCC>)),                       \
-      DD_FN((multi_regwin_kernel<_Float16, IT, TDW, NWR, NW, RPW, KMAX, FULL, OCC>)),                    \
-      DD_FN((multi_regwin_kernel<uint8_t, IT, TDW, NWR, NW, RPW, KMAX, FULL, OCC>))}}
+     {launch_regwin<float, IT, TDW, NWR, NW, RPW, KMAX>,                                           \
+      launch_regwin<_Float16, IT, TDW, NWR, NW, RPW, KMAX>,                                        \
+      launch_regwin<uint8_t, IT, TDW, NWR, NW, RPW, KMAX>},                                        \
+     {DD_FN((multi_regwin_kernel<float, IT, TDW, NWR, NW, RPW, KMAX, OCC>)),                       \
+      DD_FN((multi_regwin_kernel<_Float16, IT, TDW, NWR, NW, RPW, KMAX, OCC>)),                    \
+      DD_FN((multi_regwin_kernel<uint8_t, IT, TDW, NWR, NW, RPW, KMAX, OCC>))}}
 
 const VariantImpl kImpls[] = {
     DD_LDS_VARIANT(0, 4, 8, 4, 5.4f),   // 256 samples x 32 rows
@@ -260,16 +258,16 @@ const VariantImpl kImpls[] = {
     DD_LDS_VARIANT(7, 4, 1, 4, 2.3f),   // 256 x 4
     DD_LDS_VARIANT(8, 2, 1, 4, 2.9f),   // 128 x 4
     DD_LDS_VARIANT(9, 1, 1, 1, 0.8f),   // 64 x 1: no cross-row window, always fits
-    DD_RW_VARIANT(10, 8, 8, 40, 4, 1, 16, false, 20.1f),   // 512 x 32, register window; rates: measured T adds/s
-    DD_RW_VARIANT(11, 8, 8, 40, 4, 2, 16, false, 15.1f),   // 512 x 32, two rows per wave per chunk
-    DD_RW_VARIANT(12, 8, 4, 32, 4, 2, 16, false, 10.7f),   // 512 x 16
-    DD_RW_VARIANT(13, 16, 4, 48, 4, 1, 24, false, 18.9f),  // 1024 x 16
-    DD_RW_VARIANT(14, 4, 8, 32, 4, 2, 12, false, 15.7f),   // 256 x 32
-    DD_RW_VARIANT(15, 8, 8, 40, 8, 1, 16, false, 16.2f),   // 512 x 64, eight waves
-    DD_RW_VARIANT(16, 8, 16, 48, 4, 1, 16, false, 15.0f),  // 512 x 64, sixteen rows per wave
-    DD_RW_VARIANT(17, 8, 8, 40, 4, 1, 12, false, 23.0f),   // 512 x 32, shorter staging (fewer VGPRs)
-    DD_RW_VARIANT(18, 8, 8, 40, 4, 1, 12, true, 22.2f),    // as 17, whole window loaded per row
-    DD_RW_VARIANT(19, 8, 4, 32, 4, 1, 12, false, 19.3f),   // 512 x 16, short staging
+    DD_RW_VARIANT(10, 8, 8, 40, 4, 1, 16, 20.1f),   // 512 x 32, register window; rates: measured T adds/s
+    DD_RW_VARIANT(11, 8, 8, 40, 4, 2, 16, 15.1f),   // 512 x 32, two rows per wave per chunk
+    DD_RW_VARIANT(12, 8, 4, 32, 4, 2, 16, 10.7f),   // 512 x 16
+    DD_RW_VARIANT(13, 16, 4, 48, 4, 1, 24, 18.9f),  // 1024 x 16
+    DD_RW_VARIANT(14, 4, 8, 32, 4, 2, 12, 15.7f),   // 256 x 32
+    DD_RW_VARIANT(15, 8, 8, 40, 8, 1, 16, 16.2f),   // 512 x 64, eight waves
+    DD_RW_VARIANT(16, 8, 16, 48, 4, 1, 16, 15.0f),  // 512 x 64, sixteen rows per wave
+    DD_RW_VARIANT(17, 8, 8, 40, 4, 1, 12, 23.0f),   // 512 x 32, shorter staging (fewer VGPRs)
+    DD_RW_VARIANT(18, 8, 8, 40, 2, 1, 12, 22.0f),    // 512 x 16, two waves per group
+    DD_RW_VARIANT(19, 8, 4, 32, 4, 1, 12, 19.3f),   // 512 x 16, short staging
     DD_LDSP_VARIANT(20, 4, 8, 4, 1, 24, 10.9f),        // 256 x 32, LDS form with prefetched staging
     DD_LDSP_VARIANT(21, 4, 4, 4, 1, 16, 11.4f),        // 256 x 16
     DD_LDSP_VARIANT(22, 8, 4, 4, 1, 24, 11.0f),        // 512 x 16
@@ -279,10 +277,10 @@ const VariantImpl kImpls[] = {
     DD_LDSP_VARIANT(26, 8, 8, 4, 1, 32, 9.6f),        // 512 x 32
     DD_DIRECT_VARIANT(27, 4, 4, 4, 4.8f),             // 256 x 4, operands read straight from memory
     DD_DIRECT_VARIANT(28, 8, 4, 2, 7.3f),             // 512 x 4
-    DD_RW_VARIANT(29, 8, 4, 44, 4, 1, 12, false, 17.5f),   // 512 x 16, wide window (adjoint)
-    DD_RW_VARIANT(30, 8, 8, 76, 4, 1, 12, false, 20.8f),   // 512 x 32, wide window (adjoint)
-    DD_RW_VARIANT_OCC(31, 8, 8, 40, 8, 1, 12, false, 4, 20.0f),  // 512 x 64, eight waves, short staging
-    DD_RW_VARIANT(32, 16, 4, 48, 4, 1, 20, false, 18.0f),  // 1024 x 16, short staging
+    DD_RW_VARIANT(29, 8, 4, 44, 4, 1, 12, 17.5f),   // 512 x 16, wide window (adjoint)
+    DD_RW_VARIANT(30, 8, 8, 76, 4, 1, 12, 20.8f),   // 512 x 32, wide window (adjoint)
+    DD_RW_VARIANT_OCC(31, 8, 8, 40, 8, 1, 12, 4, 20.0f),  // 512 x 64, eight waves, short staging
+    DD_RW_VARIANT(32, 16, 4, 48, 4, 1, 20, 18.0f),  // 1024 x 16, short staging
 };
 constexpr int32_t kNumImpls = sizeof(kImpls) / sizeof(kImpls[0]);
 

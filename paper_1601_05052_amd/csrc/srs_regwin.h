@@ -14,9 +14,9 @@
 //
 // Staging: every wave owns RPW rows of each chunk of NW*RPW input rows.  Its
 // lanes fetch them with bounds-checked buffer loads (samples outside
-// [0, in_valid) read as zero) into registers two chunks ahead and write them
-// to the other of two LDS chunk buffers; one barrier per chunk.  FULL loads the
-// whole register window for every row instead of only the quads it needs.
+// [0, in_valid) read as zero; float32 rows four samples per load) into
+// registers two chunks ahead and write them to the other of two LDS chunk
+// buffers; one barrier per chunk.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -83,21 +83,48 @@ __device__ __forceinline__ uint32_t lds_address(const float *p) {
     return static_cast<uint32_t>(reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) float *)p));
 }
 
-template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX, bool FULL>
+// Quad-wide staging for float32 rows: lane l fetches samples
+// g0 + 4l + 256k .. +3 (k < KQ) with one 16-byte bounds-checked load each.
+// The buffer range is clipped as in fetch_row; dwords past it read zero.
+template <int KQ>
+__device__ __forceinline__ void fetch_row_q(const float *__restrict__ in, int64_t in_stride, int64_t in_valid,
+                                            int32_t row, int64_t g0, int32_t wcap, int lane, v4f (&pre)[KQ]) {
+    const float *rp = in + static_cast<int64_t>(row) * in_stride;
+    const int64_t end = min(in_valid, g0 + wcap);
+    const int32_t n_bytes = end > 0 ? static_cast<int32_t>(end * 4) : 0;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(rp), 0, n_bytes, kBufferFlags);
+    const uint32_t voff = static_cast<uint32_t>(g0 + 4 * lane) * 4u;  // g0 >= 0, < 2^29
+#pragma unroll
+    for (int k = 0; k < KQ; ++k)
+        pre[k] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(rs, voff + k * 1024u, 0, 0));
+}
+
+// Register-window tile.  Per (accumulator tile, wave, input row) a record of
+// RD = 1 + TDW/4 dwords: the lane window's LDS byte offset in the staged row
+// (bits 0..19) and its quad count (bits 20..), then the TDW window offsets as
+// bytes.  Records are laid out [tile][wave][row][RD] with rows padded to whole
+// chunks, so one wave's records for a group of rows are contiguous and come in
+// with a few scalar loads.  The next group's records are requested right after
+// the LDS wait of the current group's first row, so they arrive while that
+// row's additions run.
+template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX>
 __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, float *__restrict__ out,
-                                                ctab *__restrict__ base, ctab *__restrict__ wrec,
-                                                ctab *__restrict__ woff, const SrsDims &d,
-                                                int32_t tile_t, int32_t tile_a, float *lds) {
+                                                ctab *__restrict__ base, ctab *__restrict__ recs,
+                                                const SrsDims &d, int32_t tile_t, int32_t tile_a, float *lds) {
     using RW = RegWin<IT, TDW, NWR>;
     constexpr int TT = 64 * IT;
     constexpr int TA = TDW * NW;
-    constexpr int CR = NW * RPW;  // input rows per chunk
+    constexpr int CR = NW * RPW;        // input rows per chunk
+    constexpr int RD = 1 + TDW / 4;     // record dwords per (row, wave)
+    constexpr int KQ = (KMAX + 3) / 4;  // 256-sample quad pieces (float32 staging)
+    constexpr bool WIDE = sizeof(TIn) == 4;
+    static_assert(TDW % 4 == 0, "offsets are packed four to a dword");
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t t0 = static_cast<int64_t>(tile_t) * TT;
+    const int32_t n_chunks = (d.n_rows + CR - 1) / CR;
     ctab *base_tile = base + static_cast<int64_t>(tile_a) * d.n_rows;
-    ctab *wrec_tile = wrec + static_cast<int64_t>(tile_a) * d.n_rows * NW + wave;
-    ctab *woff_tile = woff + (static_cast<int64_t>(tile_a) * d.n_rows * NW + wave) * TDW;
+    ctab *rec_tile = recs + (static_cast<int64_t>(tile_a) * NW + wave) * n_chunks * (CR * RD);
     const int32_t nk = d.wcap >> 6;  // wcap is a multiple of 64
 
     typename RW::Acc acc;
@@ -111,17 +138,42 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
     const int32_t row_dw = S == 1 ? d.wcap : d.wcap / S * (S + 1);  // physical dwords per row
     const int32_t lane_st = S == 1 ? lane : 4 * ((lane >> 2) + ((lane >> 2) / S)) + (lane & 3);
     constexpr int32_t piece_dw = S == 1 ? 64 : 64 / S * (S + 1);       // physical dwords per 64 samples
+    const int32_t lane_stq = S == 1 ? 4 * lane : 4 * (lane + lane / S); // quad-wide staging: lane's quad
+    constexpr int32_t qpiece_dw = 4 * piece_dw;                         // physical dwords per 256 samples
     const int32_t buf_dw = CR * row_dw;
     const uint32_t lane_rd = lds_address(lds) + static_cast<uint32_t>(lane) * 16u * (S == 1 ? 1u : S + 1u);
 
-    float pre[RPW][KMAX];
-    const int32_t n_chunks = (d.n_rows + CR - 1) / CR;
+    // Prefetch registers: float32 rows as quads, narrower types per sample.
+    float pre[RPW][WIDE ? 1 : KMAX];
+    v4f preq[RPW][WIDE ? KQ : 1];
+    bool wide_ok[RPW];
     auto fetch_chunk = [&](int32_t c) {
 #pragma unroll
         for (int q = 0; q < RPW; ++q) {
             const int32_t row = c * CR + wave * RPW + q;
-            if (row < d.n_rows)
-                fetch_row<TIn, KMAX>(in, d.in_stride, d.in_valid, row, t0 + base_tile[row], nk, lane, pre[q]);
+            if (row < d.n_rows) {
+                const int64_t g0 = t0 + base_tile[row];
+                if constexpr (WIDE) {
+                    wide_ok[q] = g0 >= 0;
+                    if (g0 >= 0)
+                        fetch_row_q<KQ>(reinterpret_cast<const float *>(in), d.in_stride, d.in_valid, row, g0,
+                                        d.wcap, lane, preq[q]);
+                    else {  // window starts before sample 0 (adjoint near t = 0): per-sample path
+                        float tmp[KMAX];
+                        fetch_row<TIn, KMAX>(in, d.in_stride, d.in_valid, row, g0, nk, lane, tmp);
+                        // Regroup lane-strided samples (l + 64k) into this lane's quads via LDS-free
+                        // shuffles is not possible; stage them per sample instead (see store_chunk).
+#pragma unroll
+                        for (int k = 0; k < KQ; ++k)
+                            preq[q][k] = v4f{k * 4 + 0 < KMAX ? tmp[min(k * 4 + 0, KMAX - 1)] : 0.f,
+                                             k * 4 + 1 < KMAX ? tmp[min(k * 4 + 1, KMAX - 1)] : 0.f,
+                                             k * 4 + 2 < KMAX ? tmp[min(k * 4 + 2, KMAX - 1)] : 0.f,
+                                             k * 4 + 3 < KMAX ? tmp[min(k * 4 + 3, KMAX - 1)] : 0.f};
+                    }
+                } else {
+                    fetch_row<TIn, KMAX>(in, d.in_stride, d.in_valid, row, g0, nk, lane, pre[q]);
+                }
+            }
         }
     };
     auto store_chunk = [&](int32_t c) {
@@ -129,47 +181,81 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
         for (int q = 0; q < RPW; ++q) {
             const int32_t rr = wave * RPW + q;
             if (c * CR + rr < d.n_rows) {
-                float *dst = lds + (c & 1) * buf_dw + rr * row_dw + lane_st;
+                float *rowp = lds + (c & 1) * buf_dw + rr * row_dw;
+                if constexpr (WIDE) {
+                    if (wide_ok[q]) {
+                        float *dst = rowp + lane_stq;
 #pragma unroll
-                for (int k = 0; k < KMAX; ++k)
-                    if (k < nk)
-                        dst[piece_dw * k] = pre[q][k];
+                        for (int k = 0; k < KQ; ++k)
+                            if (4 * lane + 256 * k < d.wcap)
+                                *reinterpret_cast<v4f *>(dst + qpiece_dw * k) = preq[q][k];
+                    } else {
+                        // Per-sample layout: preq[q][k][i] holds sample l + 64(4k + i).
+                        float *dst = rowp + lane_st;
+#pragma unroll
+                        for (int k = 0; k < KQ; ++k)
+#pragma unroll
+                            for (int i = 0; i < 4; ++i)
+                                if (4 * k + i < nk)
+                                    dst[piece_dw * (4 * k + i)] = preq[q][k][i];
+                    }
+                } else {
+                    float *dst = rowp + lane_st;
+#pragma unroll
+                    for (int k = 0; k < KMAX; ++k)
+                        if (k < nk)
+                            dst[piece_dw * k] = pre[q][k];
+                }
             }
         }
+    };
+
+    // Records travel in groups of G rows: while group g is in use, group g+1
+    // is requested right after the LDS wait of g's first row.
+    constexpr int G = CR < 4 ? CR : 4;
+    static_assert(CR % G == 0, "record groups must tile a chunk");
+    const int32_t n_groups = n_chunks * (CR / G);
+    uint32_t cur[G * RD], nxt[G * RD];
+    auto load_recs = [&](uint32_t (&r)[G * RD], int32_t g, int dep) {
+        ctab *p = rec_tile + static_cast<int64_t>(g) * (G * RD) + dep;
+#pragma unroll
+        for (int i = 0; i < G * RD; ++i)
+            r[i] = static_cast<uint32_t>(p[i]);
     };
 
     fetch_chunk(0);
     store_chunk(0);
     if (n_chunks > 1)
         fetch_chunk(1);
+    load_recs(cur, 0, 0);
     __syncthreads();  // chunk 0 staged
     for (int32_t c = 0; c < n_chunks; ++c) {
         const int32_t r0 = c * CR;
         const int32_t nr = min(CR, d.n_rows - r0);
-        // Window records and offsets of this wave's accumulator rows for the chunk.
-        int rec[CR];
-        int o[CR][TDW];
-#pragma unroll
-        for (int rr = 0; rr < CR; ++rr) {
-            const int32_t r = min(r0 + rr, d.n_rows - 1);
-            // Wave-uniform by construction; readfirstlane keeps them in SGPRs
-            // for the assembly even where the compiler cannot prove it.
-            rec[rr] = __builtin_amdgcn_readfirstlane(wrec_tile[static_cast<int64_t>(r) * NW]);
-#pragma unroll
-            for (int a = 0; a < TDW; ++a)
-                o[rr][a] = __builtin_amdgcn_readfirstlane(woff_tile[static_cast<int64_t>(r) * NW * TDW + a]);
-        }
         const uint32_t chunk_rd = lane_rd + static_cast<uint32_t>((c & 1) * buf_dw) * 4u;
 #pragma unroll
         for (int rr = 0; rr < CR; ++rr) {
             if (rr >= nr)
                 break;
-            const uint32_t addr =
-                chunk_rd + static_cast<uint32_t>(rr * row_dw) * 4u + static_cast<uint32_t>(rec[rr] & 0xfffff);
-            if constexpr (FULL)
-                RW::row_full(acc, addr, o[rr]);
-            else
-                RW::row(acc, addr, rec[rr] >> 20, o[rr]);
+            const int gi = rr % G;
+            const uint32_t rec = __builtin_amdgcn_readfirstlane(cur[gi * RD]);
+            const uint32_t addr = chunk_rd + static_cast<uint32_t>(rr * row_dw) * 4u + (rec & 0xfffffu);
+            typename RW::Win w;
+            int dep;
+            RW::load(w, addr, static_cast<int>(rec >> 20), dep);
+            const int32_t g = (r0 + rr) / G;
+            if (gi == 0 && g + 1 < n_groups)
+                load_recs(nxt, g + 1, __builtin_amdgcn_readfirstlane(dep));
+            int o[TDW];
+#pragma unroll
+            for (int a = 0; a < TDW; ++a)
+                o[a] = __builtin_amdgcn_readfirstlane((cur[gi * RD + 1 + a / 4] >> (8 * (a % 4))) & 0xffu);
+            RW::add(acc, w, o);
+            if (gi == G - 1) {
+#pragma unroll
+                for (int i = 0; i < G * RD; ++i)
+                    cur[i] = nxt[i];
+            }
         }
         if (c + 1 < n_chunks) {
             // The other buffer was last read in chunk c-1, which every wave
