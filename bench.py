@@ -39,9 +39,9 @@ ADD_PEAK_TFLOPS = 256 * 128 * 2.4e9 / 1e12
 
 
 PROFILES = os.path.join(ROOT, "profiles")
-KERNEL_SOURCES = ["paper_1601_05052_amd/csrc/srs_regwin.h", "paper_1601_05052_amd/csrc/regwin_asm.h",
-                  "paper_1601_05052_amd/csrc/srs_tile.h", "paper_1601_05052_amd/csrc/srs_kernels.hip",
-                  "paper_1601_05052_amd/csrc/plan.cpp"]
+KERNEL_SOURCES = ["paper_1601_05052_amd/csrc/" + n for n in (
+    "srs_regwin.h", "regwin_asm.h", "srs_tile.h", "srs_launch.h", "srs_variants.def", "srs_inst.inc",
+    "srs_kernels_f32.hip", "variants.cpp", "plan.cpp")]
 
 
 def log(msg):

@@ -46,15 +46,27 @@ def compile_flags():
             "-I", INCLUDE, "-I", CSRC]
 
 
+# Kernel units compiled with -save-temps=obj: their device assembly stays in
+# _build/ (<stem>-hip-amdgcn-amd-amdhsa-gfx950.s), so tests can inspect the
+# register use of the inline-assembly kernels.
+LISTED = ("srs_kernels_f32.hip", "srs_kernels_f16.hip", "srs_kernels_u8.hip")
+
+
+def listing_paths():
+    return [os.path.join(PKG, "_build", os.path.splitext(n)[0] + "-hip-amdgcn-amd-amdhsa-gfx950.s") for n in LISTED]
+
+
 def build(verbose: bool = False, jobs: int = 8) -> str:
     """Compile every source to an object in _build/ (in parallel) and link."""
     out_dir = os.path.join(PKG, "_build")
     os.makedirs(out_dir, exist_ok=True)
     objs, procs = [], []
-    for src in sources():
+    # Largest units first so they start early.
+    for src in sorted(sources(), key=lambda p: os.path.basename(p) not in LISTED):
         obj = os.path.join(out_dir, os.path.basename(src) + ".o")
         objs.append(obj)
-        cmd = [hipcc(), "-c", "-x", "hip"] + compile_flags() + ["-o", obj, src]
+        temps = ["-save-temps=obj"] if os.path.basename(src) in LISTED else []
+        cmd = [hipcc(), "-c", "-x", "hip"] + compile_flags() + temps + ["-o", obj, src]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -46,6 +46,8 @@ CONFIGS = [
     (8, 16, 48, 24),
     (8, 4, 44, 24),   # wider windows for the adjoint (delays spread more across channels)
     (8, 8, 76, 24),
+    (8, 12, 56, 24),  # more accumulator rows per window: fewer LDS bytes per addition
+    (16, 8, 60, 24),
 ]
 
 # Register-tuple widths LLVM's AMDGPU backend can bind to one constraint.
@@ -171,7 +173,7 @@ def gen_config(it, tdw, nwr, acc0):
     L.extend(loads(w0, "addr", "nq"))
     L.append('            "s_waitcnt lgkmcnt(0)\\n\\t"')
     L.append('            "s_mov_b32 %[dep], 0\\n\\t"')
-    L.append("            : " + ", ".join(w_outs + ['[dep] "=s"(dep)']))
+    L.append("            : " + ", ".join(w_outs + ['[dep] "=&s"(dep)']))
     L.append("            : " + ", ".join(['[addr] "v"(addr)', '[nq] "s"(nq)']))
     L.append('            : "scc", "memory");')
     L.append("    }")

@@ -79,6 +79,12 @@ struct SrsArgs {
 // Element types the kernels read.
 enum InType : int32_t { IN_F32 = DD_F32, IN_F16 = DD_F16, IN_U8 = DD_U8 };
 
+namespace dev {
+struct SrsDims;
+}
+// Launcher of one variant for one input type (srs_launch.h).
+using LaunchFn = hipError_t (*)(const SrsArgs &, const dev::SrsDims &, uint32_t, size_t, hipStream_t);
+
 // Launch one shifted-row-sum problem with the given variant.
 hipError_t launch_srs(const Variant &v, int32_t in_type, const SrsArgs &a, hipStream_t stream);
 // The variant's multi-beam kernel (arguments: BatchPtrs by value, const

@@ -171,7 +171,7 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
         const int64_t rows = (int64_t)v.waves * v.rpw;
         const int64_t S = v.items_t / 4;
         const int64_t row_dw = S == 1 ? w64 : w64 / S * (S + 1);  // padded layout
-        if (2 * rows * row_dw * 4 > lds_limit || (need >> 20) != 0)   // two chunk buffers
+        if (2 * rows * row_dw * 4 > lds_limit || (need >> 20) != 0)  // two chunk buffers
             return;
         L->wcap = (int32_t)w64;
         L->rows_per_chunk = (int32_t)rows;

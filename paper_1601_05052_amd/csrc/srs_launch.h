@@ -1,4 +1,5 @@
-// Shifted-row-sum kernels for gfx950 (CDNA4), used by both directions:
+// Kernels and launch helpers of the shifted-row sum for gfx950 (CDNA4),
+// used by both directions:
 //     out[a][t] = sum_r in[r][t + O[r][a]]
 // (forward dedispersion, Sec. III-A Algorithm 1, with rows = channels and
 // accumulator rows = trial DMs; the adjoint with rows = DMs, accumulator rows =
@@ -10,6 +11,10 @@
 // lane keeps its outputs in registers, and the work-group stages each input
 // row's window in LDS once so every accumulator row of the tile reuses it
 // (the data reuse of Sec. III-A, Eq. (3)).  Only binary32 additions; no MFMA.
+//
+// Included by the per-input-type instantiation units only.
+#pragma once
+
 #include <hip/hip_runtime.h>
 
 #include "batch_desc.h"
@@ -18,8 +23,7 @@
 #include "srs_tile.h"
 
 namespace dd {
-
-namespace {
+namespace kern {
 
 using dev::SrsDims;
 
@@ -33,8 +37,10 @@ __global__ void __launch_bounds__(64 * NW)
     dev::srs_tile_lds<TIn, IT, TDW, NW>(in, out, dev::as_ctab(rel), dev::as_ctab(base), d, tile_t, tile_a, lds);
 }
 
-template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX>
-__global__ void __launch_bounds__(64 * NW)
+// OCC: waves per SIMD the register-window kernels must keep (1: no
+// constraint); set where the kernel sits at a VGPR occupancy step.
+template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX, int OCC>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC)))
     srs_regwin_kernel(const TIn *__restrict__ in, float *__restrict__ out, const int32_t *__restrict__ base,
                       const int32_t *__restrict__ recs, SrsDims d) {
     extern __shared__ __attribute__((aligned(16))) float lds_rw[];
@@ -127,8 +133,6 @@ __global__ void __launch_bounds__(64 * NW)
                                         bt.tile_t, bt.tile_a, lds_ml);
 }
 
-// OCC: waves per SIMD the multi-beam form must keep (1: no constraint); set
-// where the single-beam kernel sits exactly at a VGPR occupancy step.
 template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX, int OCC>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC)))
     multi_regwin_kernel(BatchPtrs ptrs, const BeamDesc *__restrict__ descs, const uint32_t *__restrict__ items) {
@@ -161,9 +165,7 @@ __global__ void __launch_bounds__(64 * NW)
                                          bt.d, bt.tile_t, bt.tile_a);
 }
 
-using LaunchFn = hipError_t (*)(const SrsArgs &, const SrsDims &, uint32_t, size_t, hipStream_t);
-
-hipError_t set_lds_limit(const void *fn, size_t lds) {
+inline hipError_t set_lds_limit(const void *fn, size_t lds) {
     if (lds <= 65536)
         return hipSuccess;
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
@@ -180,9 +182,9 @@ hipError_t launch_lds(const SrsArgs &a, const SrsDims &d, uint32_t blocks, size_
     return hipGetLastError();
 }
 
-template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX>
+template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX, int OCC>
 hipError_t launch_regwin(const SrsArgs &a, const SrsDims &d, uint32_t blocks, size_t lds, hipStream_t s) {
-    auto fn = srs_regwin_kernel<TIn, IT, TDW, NWR, NW, RPW, KMAX>;
+    auto fn = srs_regwin_kernel<TIn, IT, TDW, NWR, NW, RPW, KMAX, OCC>;
     hipError_t e = set_lds_limit(reinterpret_cast<const void *>(fn), lds);
     if (e != hipSuccess)
         return e;
@@ -209,136 +211,5 @@ hipError_t launch_direct(const SrsArgs &a, const SrsDims &d, uint32_t blocks, si
     return hipGetLastError();
 }
 
-struct VariantImpl {
-    Variant v;
-    LaunchFn fn[3];       // by input type: f32, f16, u8
-    const void *multi[3]; // multi-beam kernel, by input type
-};
-
-#define DD_FN(f) reinterpret_cast<const void *>(f)
-
-#define DD_LDS_VARIANT(ID, IT, TDW, NW, RATE)                                             \
-    {{ID, IT, TDW, NW, KIND_LDS, 0, 0, 0, RATE},                                                \
-     {launch_lds<float, IT, TDW, NW>, launch_lds<_Float16, IT, TDW, NW>, launch_lds<uint8_t, IT, TDW, NW>},    \
-     {DD_FN((multi_lds_kernel<float, IT, TDW, NW>)), DD_FN((multi_lds_kernel<_Float16, IT, TDW, NW>)),       \
-      DD_FN((multi_lds_kernel<uint8_t, IT, TDW, NW>))}}
-
-#define DD_LDSP_VARIANT(ID, IT, TDW, NW, RPW, KMAX, RATE)                                        \
-    {{ID, IT, TDW, NW, KIND_LDS, RPW, 0, KMAX, RATE},                                                   \
-     {launch_ldsp<float, IT, TDW, NW, RPW, KMAX>, launch_ldsp<_Float16, IT, TDW, NW, RPW, KMAX>, \
-      launch_ldsp<uint8_t, IT, TDW, NW, RPW, KMAX>},                                                    \
-     {DD_FN((multi_ldsp_kernel<float, IT, TDW, NW, RPW, KMAX>)),                                          \
-      DD_FN((multi_ldsp_kernel<_Float16, IT, TDW, NW, RPW, KMAX>)),                                       \
-      DD_FN((multi_ldsp_kernel<uint8_t, IT, TDW, NW, RPW, KMAX>))}}
-
-#define DD_DIRECT_VARIANT(ID, IT, NW, U, RATE)                                                            \
-    {{ID, IT, 1, NW, KIND_DIRECT, U, 0, 0, RATE},                                                              \
-     {launch_direct<float, IT, NW, U>, launch_direct<_Float16, IT, NW, U>, launch_direct<uint8_t, IT, NW, U>}, \
-     {DD_FN((multi_direct_kernel<float, IT, NW, U>)), DD_FN((multi_direct_kernel<_Float16, IT, NW, U>)),      \
-      DD_FN((multi_direct_kernel<uint8_t, IT, NW, U>))}}
-
-#define DD_RW_VARIANT(ID, IT, TDW, NWR, NW, RPW, KMAX, RATE) DD_RW_VARIANT_OCC(ID, IT, TDW, NWR, NW, RPW, KMAX, 1, RATE)
-#define DD_RW_VARIANT_OCC(ID, IT, TDW, NWR, NW, RPW, KMAX, OCC, RATE)                                    \
-    {{ID, IT, TDW, NW, KIND_REGWIN, RPW, NWR, KMAX, RATE},                                               \
-     {launch_regwin<float, IT, TDW, NWR, NW, RPW, KMAX>,                                           \
-      launch_regwin<_Float16, IT, TDW, NWR, NW, RPW, KMAX>,                                        \
-      launch_regwin<uint8_t, IT, TDW, NWR, NW, RPW, KMAX>},                                        \
-     {DD_FN((multi_regwin_kernel<float, IT, TDW, NWR, NW, RPW, KMAX, OCC>)),                       \
-      DD_FN((multi_regwin_kernel<_Float16, IT, TDW, NWR, NW, RPW, KMAX, OCC>)),                    \
-      DD_FN((multi_regwin_kernel<uint8_t, IT, TDW, NWR, NW, RPW, KMAX, OCC>))}}
-
-const VariantImpl kImpls[] = {
-    DD_LDS_VARIANT(0, 4, 8, 4, 5.4f),   // 256 samples x 32 rows
-    DD_LDS_VARIANT(1, 4, 4, 4, 6.3f),   // 256 x 16
-    DD_LDS_VARIANT(2, 2, 8, 4, 7.1f),   // 128 x 32
-    DD_LDS_VARIANT(3, 8, 4, 4, 3.2f),   // 512 x 16
-    DD_LDS_VARIANT(4, 4, 16, 4, 4.7f),  // 256 x 64
-    DD_LDS_VARIANT(5, 2, 16, 4, 5.3f),  // 128 x 64
-    DD_LDS_VARIANT(6, 4, 2, 4, 3.9f),   // 256 x 8
-    DD_LDS_VARIANT(7, 4, 1, 4, 2.3f),   // 256 x 4
-    DD_LDS_VARIANT(8, 2, 1, 4, 2.9f),   // 128 x 4
-    DD_LDS_VARIANT(9, 1, 1, 1, 0.8f),   // 64 x 1: no cross-row window, always fits
-    DD_RW_VARIANT(10, 8, 8, 40, 4, 1, 16, 20.1f),   // 512 x 32, register window; rates: measured T adds/s
-    DD_RW_VARIANT(11, 8, 8, 40, 4, 2, 16, 15.1f),   // 512 x 32, two rows per wave per chunk
-    DD_RW_VARIANT(12, 8, 4, 32, 4, 2, 16, 10.7f),   // 512 x 16
-    DD_RW_VARIANT(13, 16, 4, 48, 4, 1, 24, 18.9f),  // 1024 x 16
-    DD_RW_VARIANT(14, 4, 8, 32, 4, 2, 12, 15.7f),   // 256 x 32
-    DD_RW_VARIANT(15, 8, 8, 40, 8, 1, 16, 16.2f),   // 512 x 64, eight waves
-    DD_RW_VARIANT(16, 8, 16, 48, 4, 1, 16, 15.0f),  // 512 x 64, sixteen rows per wave
-    DD_RW_VARIANT(17, 8, 8, 40, 4, 1, 12, 23.0f),   // 512 x 32, shorter staging (fewer VGPRs)
-    DD_RW_VARIANT(18, 8, 8, 40, 2, 1, 12, 22.0f),    // 512 x 16, two waves per group
-    DD_RW_VARIANT(19, 8, 4, 32, 4, 1, 12, 19.3f),   // 512 x 16, short staging
-    DD_LDSP_VARIANT(20, 4, 8, 4, 1, 24, 10.9f),        // 256 x 32, LDS form with prefetched staging
-    DD_LDSP_VARIANT(21, 4, 4, 4, 1, 16, 11.4f),        // 256 x 16
-    DD_LDSP_VARIANT(22, 8, 4, 4, 1, 24, 11.0f),        // 512 x 16
-    DD_LDSP_VARIANT(23, 2, 8, 4, 2, 12, 9.6f),        // 128 x 32
-    DD_LDSP_VARIANT(24, 4, 2, 4, 2, 12, 10.3f),        // 256 x 8
-    DD_LDSP_VARIANT(25, 4, 1, 4, 2, 8, 7.2f),         // 256 x 4
-    DD_LDSP_VARIANT(26, 8, 8, 4, 1, 32, 9.6f),        // 512 x 32
-    DD_DIRECT_VARIANT(27, 4, 4, 4, 4.8f),             // 256 x 4, operands read straight from memory
-    DD_DIRECT_VARIANT(28, 8, 4, 2, 7.3f),             // 512 x 4
-    DD_RW_VARIANT(29, 8, 4, 44, 4, 1, 12, 17.5f),   // 512 x 16, wide window (adjoint)
-    DD_RW_VARIANT(30, 8, 8, 76, 4, 1, 12, 20.8f),   // 512 x 32, wide window (adjoint)
-    DD_RW_VARIANT_OCC(31, 8, 8, 40, 8, 1, 12, 4, 20.0f),  // 512 x 64, eight waves, short staging
-    DD_RW_VARIANT(32, 16, 4, 48, 4, 1, 20, 18.0f),  // 1024 x 16, short staging
-};
-constexpr int32_t kNumImpls = sizeof(kImpls) / sizeof(kImpls[0]);
-
-Variant g_variants[kNumImpls];
-bool g_variants_init = false;
-
-}  // namespace
-
-const Variant *variants(int32_t *count) {
-    if (!g_variants_init) {
-        for (int32_t i = 0; i < kNumImpls; ++i)
-            g_variants[i] = kImpls[i].v;
-        g_variants_init = true;
-    }
-    *count = kNumImpls;
-    return g_variants;
-}
-
-const Variant *find_variant(int32_t id) {
-    int32_t n = 0;
-    const Variant *vs = variants(&n);
-    return (id >= 0 && id < n) ? &vs[id] : nullptr;
-}
-
-int32_t max_lds_bytes() {
-    static int32_t cached = 0;
-    if (!cached) {
-        int dev = 0, v = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
-            cached = v;
-        else
-            cached = 160 * 1024;  // gfx950
-    }
-    return cached;
-}
-
-const void *multi_kernel(const Variant &v, int32_t in_type) { return kImpls[v.id].multi[in_type]; }
-
-hipError_t launch_srs(const Variant &v, int32_t in_type, const SrsArgs &a, hipStream_t stream) {
-    const VariantImpl &impl = kImpls[v.id];
-    SrsDims d;
-    d.in_stride = a.in_stride;
-    d.in_valid = a.in_valid;
-    d.out_stride = a.out_stride;
-    d.n_t = a.n_t;
-    d.n_acc = a.n_acc;
-    d.n_rows = a.n_rows;
-    d.wcap = a.wcap;
-    d.rows_per_chunk = a.rows_per_chunk;
-    d.n_t_tiles = static_cast<int32_t>((a.n_t + v.tt() - 1) / v.tt());
-    d.n_acc_tiles = (a.n_acc + v.ta() - 1) / v.ta();
-    const uint64_t blocks = static_cast<uint64_t>(d.n_t_tiles) * d.n_acc_tiles;
-    if (blocks == 0)
-        return hipSuccess;
-    if (blocks > 0x7fffffffull)
-        return hipErrorInvalidConfiguration;
-    return impl.fn[in_type](a, d, static_cast<uint32_t>(blocks), static_cast<size_t>(a.lds_bytes), stream);
-}
-
+}  // namespace kern
 }  // namespace dd

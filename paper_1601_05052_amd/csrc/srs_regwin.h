@@ -99,174 +99,103 @@ __device__ __forceinline__ void fetch_row_q(const float *__restrict__ in, int64_
         pre[k] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(rs, voff + k * 1024u, 0, 0));
 }
 
-// Register-window tile.  Per (accumulator tile, wave, input row) a record of
-// RD = 1 + TDW/4 dwords: the lane window's LDS byte offset in the staged row
-// (bits 0..19) and its quad count (bits 20..), then the TDW window offsets as
-// bytes.  Records are laid out [tile][wave][row][RD] with rows padded to whole
-// chunks, so one wave's records for a group of rows are contiguous and come in
-// with a few scalar loads.  The next group's records are requested right after
-// the LDS wait of the current group's first row, so they arrive while that
-// row's additions run.
-template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX>
-__device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, float *__restrict__ out,
-                                                ctab *__restrict__ base, ctab *__restrict__ recs,
-                                                const SrsDims &d, int32_t tile_t, int32_t tile_a, float *lds) {
-    using RW = RegWin<IT, TDW, NWR>;
-    constexpr int TT = 64 * IT;
-    constexpr int TA = TDW * NW;
-    constexpr int CR = NW * RPW;        // input rows per chunk
-    constexpr int RD = 1 + TDW / 4;     // record dwords per (row, wave)
-    constexpr int KQ = (KMAX + 3) / 4;  // 256-sample quad pieces (float32 staging)
-    constexpr bool WIDE = sizeof(TIn) == 4;
-    static_assert(TDW % 4 == 0, "offsets are packed four to a dword");
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t t0 = static_cast<int64_t>(tile_t) * TT;
-    const int32_t n_chunks = (d.n_rows + CR - 1) / CR;
-    ctab *base_tile = base + static_cast<int64_t>(tile_a) * d.n_rows;
-    ctab *rec_tile = recs + (static_cast<int64_t>(tile_a) * NW + wave) * n_chunks * (CR * RD);
-    const int32_t nk = d.wcap >> 6;  // wcap is a multiple of 64
-
-    typename RW::Acc acc;
-#pragma unroll
-    for (int i = 0; i < IT * TDW; ++i)
-        RW::set_acc(acc, i, 0.f);
-
-    // Padded LDS row layout (see regwin_asm.h): logical quad Q at physical
-    // quad Q + floor(Q/S) (no padding when S == 1).  Two chunk buffers.
-    constexpr int S = RW::S;
-    const int32_t row_dw = S == 1 ? d.wcap : d.wcap / S * (S + 1);  // physical dwords per row
-    const int32_t lane_st = S == 1 ? lane : 4 * ((lane >> 2) + ((lane >> 2) / S)) + (lane & 3);
-    constexpr int32_t piece_dw = S == 1 ? 64 : 64 / S * (S + 1);       // physical dwords per 64 samples
-    const int32_t lane_stq = S == 1 ? 4 * lane : 4 * (lane + lane / S); // quad-wide staging: lane's quad
-    constexpr int32_t qpiece_dw = 4 * piece_dw;                         // physical dwords per 256 samples
-    const int32_t buf_dw = CR * row_dw;
-    const uint32_t lane_rd = lds_address(lds) + static_cast<uint32_t>(lane) * 16u * (S == 1 ? 1u : S + 1u);
-
-    // Prefetch registers: float32 rows as quads, narrower types per sample.
+// Staging of input rows into padded LDS rows for the register-window forms.
+// Every wave owns RPW rows of each chunk of NW*RPW rows; fetch() loads them
+// into registers (float32 rows four samples per load, narrower types per
+// sample), store() writes them into a chunk buffer.  Padded layout: logical
+// quad Q at physical quad Q + floor(Q/S) (no padding when S == 1).
+template <typename TIn, int S, int NW, int RPW, int KMAX>
+struct ChunkStager {
+    static constexpr bool WIDE = sizeof(TIn) == 4;
+    static constexpr int KQ = (KMAX + 3) / 4;  // 256-sample quad pieces
+    static constexpr int CR = NW * RPW;
+    static constexpr int32_t piece_dw = S == 1 ? 64 : 64 / S * (S + 1);  // physical dwords per 64 samples
+    static constexpr int32_t qpiece_dw = 4 * piece_dw;                   // physical dwords per 256 samples
+    const TIn *in;
+    ctab *base_tile;
+    const SrsDims &d;
+    int64_t t0;
+    int wave, lane, nk;
+    int32_t row_dw, lane_st, lane_stq;
     float pre[RPW][WIDE ? 1 : KMAX];
     v4f preq[RPW][WIDE ? KQ : 1];
-    bool wide_ok[RPW];
-    auto fetch_chunk = [&](int32_t c) {
+    int wide_ok[RPW];  // 1: the row was fetched with quad loads (wave-uniform)
+
+    __device__ ChunkStager(const TIn *in_, ctab *base_tile_, const SrsDims &d_, int64_t t0_, int wave_, int lane_)
+        : in(in_), base_tile(base_tile_), d(d_), t0(t0_), wave(wave_), lane(lane_) {
+        nk = d.wcap >> 6;  // wcap is a multiple of 64
+        row_dw = S == 1 ? d.wcap : d.wcap / S * (S + 1);
+        lane_st = S == 1 ? lane : 4 * ((lane >> 2) + ((lane >> 2) / S)) + (lane & 3);
+        lane_stq = S == 1 ? 4 * lane : 4 * (lane + lane / S);
+    }
+
+    __device__ __forceinline__ void fetch(int32_t c) {
 #pragma unroll
         for (int q = 0; q < RPW; ++q) {
             const int32_t row = c * CR + wave * RPW + q;
             if (row < d.n_rows) {
                 const int64_t g0 = t0 + base_tile[row];
                 if constexpr (WIDE) {
-                    wide_ok[q] = g0 >= 0;
-                    if (g0 >= 0)
-                        fetch_row_q<KQ>(reinterpret_cast<const float *>(in), d.in_stride, d.in_valid, row, g0,
-                                        d.wcap, lane, preq[q]);
-                    else {  // window starts before sample 0 (adjoint near t = 0): per-sample path
+                    wide_ok[q] = __builtin_amdgcn_readfirstlane(g0 >= 0 ? 1 : 0);
+                    if (g0 >= 0) {
+                        fetch_row_q<KQ>(reinterpret_cast<const float *>(in), d.in_stride, d.in_valid, row, g0, d.wcap,
+                                        lane, preq[q]);
+                    } else {
+                        // Window starts before sample 0 (adjoint near t = 0):
+                        // per-sample loads; preq[q][k][i] holds sample
+                        // g0 + lane + 64(4k + i).
                         float tmp[KMAX];
                         fetch_row<TIn, KMAX>(in, d.in_stride, d.in_valid, row, g0, nk, lane, tmp);
-                        // Regroup lane-strided samples (l + 64k) into this lane's quads via LDS-free
-                        // shuffles is not possible; stage them per sample instead (see store_chunk).
 #pragma unroll
                         for (int k = 0; k < KQ; ++k)
-                            preq[q][k] = v4f{k * 4 + 0 < KMAX ? tmp[min(k * 4 + 0, KMAX - 1)] : 0.f,
-                                             k * 4 + 1 < KMAX ? tmp[min(k * 4 + 1, KMAX - 1)] : 0.f,
-                                             k * 4 + 2 < KMAX ? tmp[min(k * 4 + 2, KMAX - 1)] : 0.f,
-                                             k * 4 + 3 < KMAX ? tmp[min(k * 4 + 3, KMAX - 1)] : 0.f};
+#pragma unroll
+                            for (int i = 0; i < 4; ++i)
+                                preq[q][k][i] = 4 * k + i < KMAX ? tmp[min(4 * k + i, KMAX - 1)] : 0.f;
                     }
                 } else {
                     fetch_row<TIn, KMAX>(in, d.in_stride, d.in_valid, row, g0, nk, lane, pre[q]);
                 }
             }
         }
-    };
-    auto store_chunk = [&](int32_t c) {
+    }
+
+    // Write the fetched rows of chunk c into the chunk buffer at buf.
+    __device__ __forceinline__ void store(int32_t c, float *buf) const {
 #pragma unroll
         for (int q = 0; q < RPW; ++q) {
             const int32_t rr = wave * RPW + q;
             if (c * CR + rr < d.n_rows) {
-                float *rowp = lds + (c & 1) * buf_dw + rr * row_dw;
+                float *rowp = buf + rr * row_dw;
                 if constexpr (WIDE) {
                     if (wide_ok[q]) {
-                        float *dst = rowp + lane_stq;
 #pragma unroll
                         for (int k = 0; k < KQ; ++k)
                             if (4 * lane + 256 * k < d.wcap)
-                                *reinterpret_cast<v4f *>(dst + qpiece_dw * k) = preq[q][k];
+                                *reinterpret_cast<v4f *>(rowp + lane_stq + qpiece_dw * k) = preq[q][k];
                     } else {
-                        // Per-sample layout: preq[q][k][i] holds sample l + 64(4k + i).
-                        float *dst = rowp + lane_st;
 #pragma unroll
                         for (int k = 0; k < KQ; ++k)
 #pragma unroll
                             for (int i = 0; i < 4; ++i)
                                 if (4 * k + i < nk)
-                                    dst[piece_dw * (4 * k + i)] = preq[q][k][i];
+                                    rowp[lane_st + piece_dw * (4 * k + i)] = preq[q][k][i];
                     }
                 } else {
-                    float *dst = rowp + lane_st;
 #pragma unroll
                     for (int k = 0; k < KMAX; ++k)
                         if (k < nk)
-                            dst[piece_dw * k] = pre[q][k];
+                            rowp[lane_st + piece_dw * k] = pre[q][k];
                 }
             }
         }
-    };
-
-    // Records travel in groups of G rows: while group g is in use, group g+1
-    // is requested right after the LDS wait of g's first row.
-    constexpr int G = CR < 4 ? CR : 4;
-    static_assert(CR % G == 0, "record groups must tile a chunk");
-    const int32_t n_groups = n_chunks * (CR / G);
-    uint32_t cur[G * RD], nxt[G * RD];
-    auto load_recs = [&](uint32_t (&r)[G * RD], int32_t g, int dep) {
-        ctab *p = rec_tile + static_cast<int64_t>(g) * (G * RD) + dep;
-#pragma unroll
-        for (int i = 0; i < G * RD; ++i)
-            r[i] = static_cast<uint32_t>(p[i]);
-    };
-
-    fetch_chunk(0);
-    store_chunk(0);
-    if (n_chunks > 1)
-        fetch_chunk(1);
-    load_recs(cur, 0, 0);
-    __syncthreads();  // chunk 0 staged
-    for (int32_t c = 0; c < n_chunks; ++c) {
-        const int32_t r0 = c * CR;
-        const int32_t nr = min(CR, d.n_rows - r0);
-        const uint32_t chunk_rd = lane_rd + static_cast<uint32_t>((c & 1) * buf_dw) * 4u;
-#pragma unroll
-        for (int rr = 0; rr < CR; ++rr) {
-            if (rr >= nr)
-                break;
-            const int gi = rr % G;
-            const uint32_t rec = __builtin_amdgcn_readfirstlane(cur[gi * RD]);
-            const uint32_t addr = chunk_rd + static_cast<uint32_t>(rr * row_dw) * 4u + (rec & 0xfffffu);
-            typename RW::Win w;
-            int dep;
-            RW::load(w, addr, static_cast<int>(rec >> 20), dep);
-            const int32_t g = (r0 + rr) / G;
-            if (gi == 0 && g + 1 < n_groups)
-                load_recs(nxt, g + 1, __builtin_amdgcn_readfirstlane(dep));
-            int o[TDW];
-#pragma unroll
-            for (int a = 0; a < TDW; ++a)
-                o[a] = __builtin_amdgcn_readfirstlane((cur[gi * RD + 1 + a / 4] >> (8 * (a % 4))) & 0xffu);
-            RW::add(acc, w, o);
-            if (gi == G - 1) {
-#pragma unroll
-                for (int i = 0; i < G * RD; ++i)
-                    cur[i] = nxt[i];
-            }
-        }
-        if (c + 1 < n_chunks) {
-            // The other buffer was last read in chunk c-1, which every wave
-            // finished before the previous barrier.
-            store_chunk(c + 1);
-            if (c + 2 < n_chunks)
-                fetch_chunk(c + 2);
-            __syncthreads();  // chunk c+1 staged; chunk c consumed by every wave
-        }
     }
+};
 
+// Store a wave's accumulators: lane l holds samples t0 + IT*l .. +IT-1 of
+// accumulator rows tile_a*TA + wave*TDW + a.
+template <typename RW, int IT, int TDW, int TA>
+__device__ __forceinline__ void store_acc(const typename RW::Acc &acc, float *__restrict__ out, const SrsDims &d,
+                                          int64_t t0, int32_t tile_a, int wave, int lane) {
     const int64_t tl = t0 + static_cast<int64_t>(lane) * IT;
 #pragma unroll
     for (int a = 0; a < TDW; ++a) {
@@ -292,6 +221,99 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
                     dst[j] = RW::get_acc(acc, a * IT + j);
         }
     }
+}
+
+// Register-window tile.  Per (accumulator tile, wave, input row) a record of
+// RD = 1 + TDW/4 dwords: the lane window's LDS byte offset in the staged row
+// (bits 0..19) and its quad count (bits 20..), then the TDW window offsets as
+// bytes.  Records are laid out [tile][wave][row][RD] with rows padded to whole
+// chunks, so one wave's records for a group of rows are contiguous and come in
+// with a few scalar loads.  The next group's records are requested right after
+// the LDS wait of the current group's first row, so they arrive while that
+// row's additions run.
+template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX>
+__device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, float *__restrict__ out,
+                                                ctab *__restrict__ base, ctab *__restrict__ recs,
+                                                const SrsDims &d, int32_t tile_t, int32_t tile_a, float *lds) {
+    using RW = RegWin<IT, TDW, NWR>;
+    constexpr int TT = 64 * IT;
+    constexpr int TA = TDW * NW;
+    constexpr int CR = NW * RPW;     // input rows per chunk
+    constexpr int RD = 1 + TDW / 4;  // record dwords per (row, wave)
+    constexpr int S = RW::S;
+    static_assert(TDW % 4 == 0, "offsets are packed four to a dword");
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t t0 = static_cast<int64_t>(tile_t) * TT;
+    const int32_t n_chunks = (d.n_rows + CR - 1) / CR;
+    ctab *rec_tile = recs + (static_cast<int64_t>(tile_a) * NW + wave) * n_chunks * (CR * RD);
+
+    typename RW::Acc acc;
+#pragma unroll
+    for (int i = 0; i < IT * TDW; ++i)
+        RW::set_acc(acc, i, 0.f);
+
+    ChunkStager<TIn, S, NW, RPW, KMAX> st(in, base + static_cast<int64_t>(tile_a) * d.n_rows, d, t0, wave, lane);
+    const int32_t buf_dw = CR * st.row_dw;  // two chunk buffers
+    const uint32_t lane_rd = lds_address(lds) + static_cast<uint32_t>(lane) * 16u * (S == 1 ? 1u : S + 1u);
+
+    // Records travel in groups of G rows: while group g is in use, group g+1
+    // is requested right after the LDS wait of g's first row.
+    constexpr int G = CR < 4 ? CR : 4;
+    static_assert(CR % G == 0, "record groups must tile a chunk");
+    const int32_t n_groups = n_chunks * (CR / G);
+    uint32_t cur[G * RD], nxt[G * RD];
+    auto load_recs = [&](uint32_t (&r)[G * RD], int32_t g, int dep) {
+        ctab *p = rec_tile + static_cast<int64_t>(g) * (G * RD) + dep;
+#pragma unroll
+        for (int i = 0; i < G * RD; ++i)
+            r[i] = static_cast<uint32_t>(p[i]);
+    };
+
+    st.fetch(0);
+    st.store(0, lds);
+    if (n_chunks > 1)
+        st.fetch(1);
+    load_recs(cur, 0, 0);
+    __syncthreads();  // chunk 0 staged
+    for (int32_t c = 0; c < n_chunks; ++c) {
+        const int32_t r0 = c * CR;
+        const int32_t nr = min(CR, d.n_rows - r0);
+        const uint32_t chunk_rd = lane_rd + static_cast<uint32_t>((c & 1) * buf_dw) * 4u;
+#pragma unroll
+        for (int rr = 0; rr < CR; ++rr) {
+            if (rr >= nr)
+                break;
+            const int gi = rr % G;
+            const uint32_t rec = __builtin_amdgcn_readfirstlane(cur[gi * RD]);
+            const uint32_t addr = chunk_rd + static_cast<uint32_t>(rr * st.row_dw) * 4u + (rec & 0xfffffu);
+            typename RW::Win w;
+            int dep;
+            RW::load(w, addr, static_cast<int>(rec >> 20), dep);
+            const int32_t g = (r0 + rr) / G;
+            if (gi == 0 && g + 1 < n_groups)
+                load_recs(nxt, g + 1, __builtin_amdgcn_readfirstlane(dep));
+            int o[TDW];
+#pragma unroll
+            for (int a = 0; a < TDW; ++a)
+                o[a] = __builtin_amdgcn_readfirstlane((cur[gi * RD + 1 + a / 4] >> (8 * (a % 4))) & 0xffu);
+            RW::add(acc, w, o);
+            if (gi == G - 1) {
+#pragma unroll
+                for (int i = 0; i < G * RD; ++i)
+                    cur[i] = nxt[i];
+            }
+        }
+        if (c + 1 < n_chunks) {
+            // The other buffer was last read in chunk c-1, which every wave
+            // finished before the previous barrier.
+            st.store(c + 1, lds + ((c + 1) & 1) * buf_dw);
+            if (c + 2 < n_chunks)
+                st.fetch(c + 2);
+            __syncthreads();  // chunk c+1 staged; chunk c consumed by every wave
+        }
+    }
+    store_acc<RW, IT, TDW, TA>(acc, out, d, t0, tile_a, wave, lane);
 }
 
 // LDS form with prefetch: the staging of srs_tile_regwin (bounds-checked
