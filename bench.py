@@ -65,9 +65,11 @@ def measured_traffic(workload, variant):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_hash") != kernel_source_hash() or t.get("variant") != variant:
+    if t.get("source_hash") != kernel_source_hash():
         return None
-    return t.get("traffic_bytes")
+    if t.get("variant") == variant:
+        return t.get("traffic_bytes")
+    return t.get("by_variant", {}).get(str(variant))
 
 
 def compulsory_bytes(setup, in_bytes_per_sample, plan):
