@@ -58,7 +58,7 @@ def kernel_source_hash():
             data = f.read()
         if rel.endswith(".def"):
             text = re.sub(r"/\*.*?\*/|//[^\n]*", "", data.decode(), flags=re.S)
-            data = re.sub(r",\s*[0-9.]+f\)", ")", text).encode()
+            data = re.sub(r"\s+", " ", re.sub(r",\s*[0-9.]+f\)", ")", text)).encode()
         h.update(data)
     return h.hexdigest()[:16]
 
