@@ -29,6 +29,8 @@
 namespace dd {
 namespace dev {
 
+typedef int v4i __attribute__((ext_vector_type(4)));
+
 constexpr uint32_t kBufferFlags = 0x00020000u;  // raw buffer, 32-bit data format (gfx9 V# word 3)
 constexpr uint32_t kOutOfRange = 0x80000000u;   // any offset >= num_records reads 0
 
@@ -367,21 +369,76 @@ __device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float 
         }
     };
 
+    // This wave's offsets for a chunk (CR rows x TDW accumulator rows) come in
+    // with wave-uniform vector loads (every lane the same address), held in
+    // VGPRs (scalar registers would run out), two chunks ahead like the
+    // staging data, so no row waits for them.
+    const __amdgpu_buffer_rsrc_t rel_rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<int32_t *>(reinterpret_cast<const int32_t *>(reinterpret_cast<uintptr_t>(rel_tile))), 0,
+        0x7fffffff, kBufferFlags);
+    // Small chunks only (CR*TDW <= 16): larger ones read each row's offsets
+    // with scalar loads as they go.
+    constexpr bool PREF = CR * TDW <= 16;
+    constexpr int OR = PREF ? CR : 1, OK = PREF ? TDW : 1;
+    int32_t ocur[OR][OK], onxt[OR][OK], onxt2[OR][OK];
+    auto load_offsets = [&](int32_t (&o)[OR][OK], int32_t c) {
+        if constexpr (PREF) {
+#pragma unroll
+        for (int rr = 0; rr < CR; ++rr) {
+            const int32_t r = min(c * CR + rr, d.n_rows - 1);
+            const uint32_t off = static_cast<uint32_t>(r * TA) * 4u;  // within this tile's table
+            if constexpr (TDW % 4 == 0) {
+#pragma unroll
+                for (int k = 0; k < TDW; k += 4) {
+                    const v4i v = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rel_rs, off + 4u * k, 0, 0));
+                    o[rr][k] = v.x;
+                    o[rr][k + 1] = v.y;
+                    o[rr][k + 2] = v.z;
+                    o[rr][k + 3] = v.w;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < TDW; ++k)
+                    o[rr][k] = static_cast<int32_t>(__builtin_amdgcn_raw_buffer_load_b32(rel_rs, off + 4u * k, 0, 0));
+            }
+        }
+        }
+    };
+
     fetch_chunk(0);
     store_chunk(0);
     if (n_chunks > 1)
         fetch_chunk(1);
+    if constexpr (PREF) {
+        load_offsets(onxt, 0);
+        if (n_chunks > 1)
+            load_offsets(onxt2, 1);
+    }
     __syncthreads();
     for (int32_t c = 0; c < n_chunks; ++c) {
         const int32_t r0 = c * CR;
         const int32_t nr = min(CR, d.n_rows - r0);
         const float *buf = lds + (c & 1) * buf_dw + lane;
-        for (int32_t rr = 0; rr < nr; ++rr) {
-            ctab *o = rel_tile + static_cast<int64_t>(r0 + rr) * TA;
+#pragma unroll
+        for (int rr = 0; rr < OR; ++rr)
+#pragma unroll
+            for (int k = 0; k < OK; ++k) {
+                ocur[rr][k] = onxt[rr][k];
+                onxt[rr][k] = onxt2[rr][k];
+            }
+#pragma unroll
+        for (int rr = 0; rr < CR; ++rr) {
+            if (rr >= nr)
+                break;
             const float *row = buf + rr * d.wcap;
 #pragma unroll
             for (int k = 0; k < TDW; ++k) {
-                const float *p = row + __builtin_amdgcn_readfirstlane(o[k]);
+                int32_t ok;
+                if constexpr (PREF)
+                    ok = ocur[rr % OR][k % OK];
+                else
+                    ok = __builtin_amdgcn_readfirstlane(rel_tile[static_cast<int64_t>(r0 + rr) * TA + k]);
+                const float *p = row + ok;
 #pragma unroll
                 for (int j = 0; j < IT; ++j)
                     acc[k][j] += p[64 * j];
@@ -389,8 +446,16 @@ __device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float 
         }
         if (c + 1 < n_chunks) {
             store_chunk(c + 1);
-            if (c + 2 < n_chunks)
+            if (c + 2 < n_chunks) {
+                // Chunk c+2's offsets go out just ahead of its staging loads;
+                // they are used after that staging data has been stored, so
+                // waiting for them never waits on newer loads.
+                if constexpr (PREF) {
+                    load_offsets(onxt2, c + 2);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
                 fetch_chunk(c + 2);
+            }
             __syncthreads();
         }
     }
