@@ -260,7 +260,8 @@ def main():
     achieved_tflops = setup.adds / (ms * 1e-3) / 1e12
     hbm_gbps = r["compulsory_bytes"] / (ms * 1e-3) / 1e9
     line = {
-        "metric": "dedispersion GFLOP/s (one FLOP per channel addition), Apertif-shaped beam, FP32",
+        "metric": "dedispersion GFLOP/s (one FLOP per channel addition), %s-shaped beam, FP32"
+                  % {"apertif": "Apertif", "lofar": "LOFAR"}[args.workload],
         "value": round(r["gflops"], 2),
         "unit": "GFLOP/s",
         "n_gpus": 1,
