@@ -23,8 +23,9 @@ S*l + c (c a multiple of S) has its q-th quad at physical
 (S+1)*l + (c + c/S) + q + floor(q/S): a per-lane base plus compile-time
 offsets.
 
-Only the quads a row needs are loaded: the first S unconditionally, the rest
-behind a compare-and-branch on the row's quad count.  Accumulators and the
+Only the quads a row needs are loaded (rounded up to a pair past the first
+S): the first S unconditionally, the rest two at a time behind a
+compare-and-branch on the row's quad count.  Accumulators and the
 window are pinned with explicit-register constraints; the window is the
 output of load() and an input of add(), so scalar work can be placed between
 the LDS wait and the additions.
@@ -111,9 +112,12 @@ def gen_config(it, tdw, nwr, acc0):
         reg += n
 
     def loads(win0, addr, nq):
+        # Quads past the first S come in pairs behind one compare-and-branch:
+        # at most one quad more than the row needs is read (the layout keeps
+        # it inside the staged row), for half the scalar instructions.
         out = []
         for q in range(nq_max):
-            if q >= s:
+            if q >= s and (q - s) % 2 == 0:
                 out.append('            "s_cmp_lt_u32 %%[%s], %d\\n\\t"' % (nq, q + 1))
                 out.append('            "s_cbranch_scc1 L_rw_ld_%=\\n\\t"')
             out.append('            "ds_read_b128 v[%d:%d], %%[%s] offset:%d\\n\\t"'

@@ -121,7 +121,10 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
                     ok = false;  // this wave's delays spread wider than its register window
                     break;
                 }
-                need = std::max<int64_t>(need, (int64_t)63 * v.items_t + ws + 4 * nq);
+                // Quads past the first S are loaded in pairs (regwin_asm.h): the
+                // staged row must hold the rounded-up count, capped at the window.
+                const int32_t nq_loaded = std::min(v.nwr / 4, S + (nq - S + 1) / 2 * 2);
+                need = std::max<int64_t>(need, (int64_t)63 * v.items_t + ws + 4 * std::max(nq, nq_loaded));
                 if (build) {
                     const int32_t c = ws / 4;
                     const int32_t u_bytes = 16 * (S == 1 ? c : c + c / S);  // padded LDS layout
