@@ -169,16 +169,29 @@ def gen_config(it, tdw, nwr, acc0):
 
     # Load nq window quads from LDS byte address `addr` and wait for them; dep
     # is an SGPR set to 0 after the wait (a data dependence that keeps later
-    # scalar loads from being scheduled above it).
+    # scalar loads from being scheduled above it).  The row's packed offsets
+    # pk (four bytes per dword) are unpacked into o[] between issuing the LDS
+    # reads and waiting for them, so that scalar work overlaps their latency.
     L.append("    // addr: LDS byte address of this lane's first window quad; nq: quads to")
     L.append("    // load (NQ_MIN <= nq <= NQ_MAX).  Quads past nq are left undefined.")
-    L.append("    __device__ static __forceinline__ void load(Win &w, uint32_t addr, int nq, int &dep) {")
+    L.append("    // pk: the row's window offsets, four bytes per dword; o: unpacked.")
+    L.append("    __device__ static __forceinline__ void load(Win &w, uint32_t addr, int nq, const uint32_t (&pk)[%d],"
+             % (tdw // 4))
+    L.append("                                                int (&o)[%d], int &dep) {" % tdw)
     L.append("        asm volatile(")
     L.extend(loads(w0, "addr", "nq"))
+    for a in range(tdw):
+        if a % 4 == 0:
+            L.append('            "s_and_b32 %%[o%d], %%[pk%d], 0xff\\n\\t"' % (a, a // 4))
+        elif a % 4 == 3:
+            L.append('            "s_lshr_b32 %%[o%d], %%[pk%d], 24\\n\\t"' % (a, a // 4))
+        else:
+            L.append('            "s_bfe_u32 %%[o%d], %%[pk%d], 0x%x\\n\\t"' % (a, a // 4, 0x80000 | (8 * (a % 4))))
     L.append('            "s_waitcnt lgkmcnt(0)\\n\\t"')
     L.append('            "s_mov_b32 %[dep], 0\\n\\t"')
-    L.append("            : " + ", ".join(w_outs + ['[dep] "=&s"(dep)']))
-    L.append("            : " + ", ".join(['[addr] "v"(addr)', '[nq] "s"(nq)']))
+    L.append("            : " + ", ".join(w_outs + ['[o%d] "=&s"(o[%d])' % (a, a) for a in range(tdw)] + ['[dep] "=&s"(dep)']))
+    L.append("            : " + ", ".join(['[addr] "v"(addr)', '[nq] "s"(nq)'] +
+                                 ['[pk%d] "s"(pk[%d])' % (k, k) for k in range(tdw // 4)]))
     L.append('            : "scc", "memory");')
     L.append("    }")
     # Add the window at every accumulator row's offset o[a].

@@ -291,14 +291,15 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
             const uint32_t addr = chunk_rd + static_cast<uint32_t>(rr * st.row_dw) * 4u + (rec & 0xfffffu);
             typename RW::Win w;
             int dep;
-            RW::load(w, addr, static_cast<int>(rec >> 20), dep);
+            uint32_t pk[TDW / 4];
+#pragma unroll
+            for (int k = 0; k < TDW / 4; ++k)
+                pk[k] = __builtin_amdgcn_readfirstlane(cur[gi * RD + 1 + k]);
+            int o[TDW];
+            RW::load(w, addr, static_cast<int>(rec >> 20), pk, o, dep);
             const int32_t g = (r0 + rr) / G;
             if (gi == 0 && g + 1 < n_groups)
                 load_recs(nxt, g + 1, __builtin_amdgcn_readfirstlane(dep));
-            int o[TDW];
-#pragma unroll
-            for (int a = 0; a < TDW; ++a)
-                o[a] = __builtin_amdgcn_readfirstlane((cur[gi * RD + 1 + a / 4] >> (8 * (a % 4))) & 0xffu);
             RW::add(acc, w, o);
             if (gi == G - 1) {
 #pragma unroll
