@@ -259,12 +259,15 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
     const int32_t buf_dw = CR * st.row_dw;  // two chunk buffers
     const uint32_t lane_rd = lds_address(lds) + static_cast<uint32_t>(lane) * 16u * (S == 1 ? 1u : S + 1u);
 
-    // Records travel in groups of G rows: while group g is in use, group g+1
-    // is requested right after the LDS wait of g's first row.
-    constexpr int G = CR < 4 ? CR : 4;
-    static_assert(CR % G == 0, "record groups must tile a chunk");
-    const int32_t n_groups = n_chunks * (CR / G);
-    uint32_t cur[G * RD], nxt[G * RD];
+    // Records travel in groups of G = CR/2 rows, two per chunk, held in two
+    // register sets used alternately (set 0: rows 0..G-1, set 1: rows
+    // G..CR-1), so no copies are needed.  While one set is in use the other
+    // is refilled with the next group, requested right after the LDS wait of
+    // the current group's first row.
+    constexpr int G = CR / 2;
+    static_assert(CR % 2 == 0, "two record groups per chunk");
+    const int32_t n_groups = n_chunks * 2;
+    uint32_t rs0[G * RD], rs1[G * RD];
     auto load_recs = [&](uint32_t (&r)[G * RD], int32_t g, int dep) {
         ctab *p = rec_tile + static_cast<int64_t>(g) * (G * RD) + dep;
 #pragma unroll
@@ -276,7 +279,7 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
     st.store(0, lds);
     if (n_chunks > 1)
         st.fetch(1);
-    load_recs(cur, 0, 0);
+    load_recs(rs0, 0, 0);
     __syncthreads();  // chunk 0 staged
     for (int32_t c = 0; c < n_chunks; ++c) {
         const int32_t r0 = c * CR;
@@ -287,6 +290,9 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
             if (rr >= nr)
                 break;
             const int gi = rr % G;
+            const bool second = rr >= G;  // which record set holds this row
+            uint32_t(&cur)[G * RD] = second ? rs1 : rs0;
+            uint32_t(&oth)[G * RD] = second ? rs0 : rs1;
             const uint32_t rec = __builtin_amdgcn_readfirstlane(cur[gi * RD]);
             const uint32_t addr = chunk_rd + static_cast<uint32_t>(rr * st.row_dw) * 4u + (rec & 0xfffffu);
             typename RW::Win w;
@@ -297,15 +303,10 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
                 pk[k] = __builtin_amdgcn_readfirstlane(cur[gi * RD + 1 + k]);
             int o[TDW];
             RW::load(w, addr, static_cast<int>(rec >> 20), pk, o, dep);
-            const int32_t g = (r0 + rr) / G;
+            const int32_t g = 2 * c + (second ? 1 : 0);
             if (gi == 0 && g + 1 < n_groups)
-                load_recs(nxt, g + 1, __builtin_amdgcn_readfirstlane(dep));
+                load_recs(oth, g + 1, __builtin_amdgcn_readfirstlane(dep));
             RW::add(acc, w, o);
-            if (gi == G - 1) {
-#pragma unroll
-                for (int i = 0; i < G * RD; ++i)
-                    cur[i] = nxt[i];
-            }
         }
         if (c + 1 < n_chunks) {
             // The other buffer was last read in chunk c-1, which every wave
