@@ -18,6 +18,7 @@ adjoint and fwd+bwd step, and the 64-beam batched launch.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import re
 import json
@@ -157,6 +158,40 @@ def cpu_baseline(setup, budget_s=12.0):
                                                  setup.n_samples, reps, adds, dt)}
 
 
+def realtime(torch, dd, stream, n_chunks):
+    """Real-time check (Sec. V, V-D): one-second u8 chunks of an Apertif-shaped
+    beam pushed from pinned host memory; the host-to-device copy of each chunk
+    overlaps the previous chunk's kernels.  Beams per GPU = one second of data
+    over the time per pushed second (copies included)."""
+    s = synth.APERTIF
+    plan = dd.Plan.from_setup(s)
+    plan.autotune(dd.DD_FORWARD, dd.DD_U8, reps=3)
+    rt = dd.Realtime(plan, torch.uint8)
+    g = torch.Generator().manual_seed(s.seed)
+    chunks = [torch.randint(0, 256, (s.n_channels, s.n_samples), dtype=torch.uint8, generator=g).pin_memory()
+              for _ in range(2)]
+    outs = [torch.empty((s.n_dm, s.n_samples), device="cuda") for _ in range(2)]
+    k = [0]
+
+    def push():
+        rt.push(chunks[k[0] % 2], out=outs[k[0] % 2])
+        k[0] += 1
+
+    ms_ev, wall = timed(torch, push, n_chunks, 3, stream)
+    ms = max(ms_ev, wall / n_chunks * 1e3)
+    dev = torch.empty((s.n_channels, s.n_samples), dtype=torch.uint8, device="cuda")
+    ms_h2d, _ = timed(torch, lambda: dev.copy_(chunks[0], non_blocking=True), n_chunks, 2, stream)
+    chunk_s = s.n_samples * s.t_samp
+    rt.close()
+    r = dict(ms_per_chunk=ms, chunk_seconds=chunk_s, realtime_beams_per_gpu=chunk_s / (ms * 1e-3),
+             gflops_incl_copies=s.adds / (ms * 1e-3) / 1e9, h2d_ms=ms_h2d,
+             h2d_GBps=s.n_channels * s.n_samples / (ms_h2d * 1e-3) / 1e9, tile=plan.get_tile(dtype=dd.DD_U8),
+             note="pinned u8 chunks, copy stream + compute stream, wall clock per pushed second")
+    log("realtime apertif u8: %.3f ms per 1 s chunk (H2D alone %.3f ms, %.1f GB/s): %.0f beams in real time"
+        % (ms, ms_h2d, r["h2d_GBps"], r["realtime_beams_per_gpu"]))
+    return r
+
+
 def extras(torch, dd, stream, steps):
     res = {}
     # LOFAR-shaped beam, float32
@@ -169,6 +204,14 @@ def extras(torch, dd, stream, steps):
         r, _ = measure_forward(torch, dd, synth.APERTIF, dt, steps, 2, stream)
         res["apertif_" + dt] = r
         log("apertif %s: %.3f ms %.1f GFLOP/s" % (dt, r["ms"], r["gflops"]))
+    # perfect-reuse limit (Sec. IV-C / V-C): every trial DM is 0, tuned again
+    for base in (synth.APERTIF, synth.LOFAR):
+        z = dataclasses.replace(base, name=base.name + "_0dm", dm_step=0.0)
+        r, _ = measure_forward(torch, dd, z, "f32", steps, 2, stream)
+        res[z.name] = r
+        log("%s: %.3f ms %.1f GFLOP/s (variant %d)" % (z.name, r["ms"], r["gflops"], r["tile"]))
+    # streaming: one Apertif beam fed second by second from pinned host memory
+    res["realtime_apertif_u8"] = realtime(torch, dd, stream, max(10, steps // 2))
     # adjoint and fwd+bwd (8 Apertif-shaped beams through autograd)
     beams = synth.fwd_bwd_beams()
     plans = [dd.Plan.from_setup(b) for b in beams]
@@ -223,6 +266,55 @@ def extras(torch, dd, stream, steps):
     return res
 
 
+def tune_study(torch, dd, stream, reps=5):
+    """Auto-tuning study (Sec. IV-A / IV-B, V-A / V-B): for each setup and each
+    instance of 2^1 .. 2^12 trial DMs (one second of data), time every tile
+    variant that fits, and report the optimum, the mean and spread over the
+    optimisation space, the optimum's signal-to-noise ratio with its Chebyshev
+    bound, the best single fixed variant per setup, and the cost model's
+    untuned choice."""
+    variants = [v[0] for v in dd.tile_variants()]
+    study = []
+    for base in (synth.APERTIF, synth.LOFAR):
+        rows = []
+        for e in range(1, 13):
+            st = dataclasses.replace(base, name="%s_%d" % (base.name, 2 ** e), n_dm=2 ** e)
+            plan = dd.Plan.from_setup(st)
+            x = gpu_input(torch, st, plan.input_samples, "f32", st.seed)
+            out = torch.empty((st.n_dm, st.n_samples), device="cuda")
+            gf = {}
+            for vid in variants:
+                try:
+                    plan.set_tile(vid)
+                except dd.DedispError:
+                    continue   # the tile's window does not fit this instance
+                ms, _ = timed(torch, lambda: dd.dedisperse(x, plan, out=out), reps, 2, stream)
+                gf[vid] = st.adds / (ms * 1e-3) / 1e9
+            plan.set_tile(-1)
+            model = plan.get_tile()
+            vals = np.array(list(gf.values()))
+            best = max(gf, key=gf.get)
+            snr = (gf[best] - vals.mean()) / vals.std() if vals.std() > 0 else float("inf")
+            rows.append(dict(setup=base.name, n_dm=st.n_dm, n_variants=len(gf), best=best,
+                             best_gflops=gf[best], mean_gflops=float(vals.mean()), std_gflops=float(vals.std()),
+                             snr=snr, chebyshev_bound=min(1.0, 1.0 / snr ** 2) if snr > 0 else 1.0,
+                             model_variant=model, model_gflops=gf.get(model),
+                             realtime=st.adds / (gf[best] * 1e9) < st.n_samples * st.t_samp,
+                             gflops={str(k): round(v, 1) for k, v in gf.items()}))
+            log("%s %4d DMs: %d variants, best %d at %.0f GFLOP/s, mean %.0f, SNR %.2f, model %d"
+                % (base.name, st.n_dm, len(gf), best, gf[best], vals.mean(), snr, model))
+            del x, out
+            torch.cuda.empty_cache()
+        # best single fixed variant: fits every instance, highest geometric-mean rate
+        common = set.intersection(*[set(int(k) for k in r["gflops"]) for r in rows])
+        fixed = max(common, key=lambda v: sum(np.log(r["gflops"][str(v)]) for r in rows))
+        for r in rows:
+            r["fixed_variant"] = fixed
+            r["tuned_over_fixed"] = r["best_gflops"] / r["gflops"][str(fixed)]
+        study += rows
+    return study
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -231,6 +323,8 @@ def main():
     ap.add_argument("--workload", default="apertif", choices=["apertif", "lofar"])
     ap.add_argument("--no-extra", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-study", metavar="JSON",
+                    help="run the auto-tuning study over 2..4096 DMs for both setups, write it here, exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
@@ -245,6 +339,11 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     setup = synth.WORKLOADS[args.workload]
+    if args.tune_study:
+        study = tune_study(torch, dd, stream)
+        with open(args.tune_study, "w") as f:
+            json.dump(study, f, indent=1)
+        return
 
     # Headline input: the seeded workload with its pulses (arrivals from the
     # library's own plan; the timing does not depend on the values).

@@ -209,6 +209,52 @@ int dd_batch_variants(const dd_batch *batch, int32_t *variants);
 
 int dd_batch_destroy(dd_batch *batch);
 
+/* ---------------------------------------------------------------- real time */
+
+/* Streaming dedispersion of one beam, one chunk of n_samples at a time.  The
+ * method's step dedisperses one second of data, reading the samples its
+ * largest delay reaches past that second (Sec. III-A); real time means each
+ * second is dedispersed in under a second (Sec. V, Sec. V-D).  The object keeps
+ * the last T_in = n_samples + max_delay input samples of every channel on the
+ * device (zeros before the first push).  Push k (k = 0, 1, ...) appends
+ * samples [k*S, (k+1)*S) of the stream (S = n_samples) and writes
+ *     out[i][t] = sum_ch x[ch][k*S - max_delay + t + delay[i][ch]],  t < S,
+ * where x is the pushed stream with x = 0 before time 0: consecutive pushes
+ * produce consecutive, non-overlapping output times, max_delay samples behind
+ * the newest input.
+ *
+ * dd_realtime_create binds the plan (which must outlive the object), the
+ * input type and the compute stream; it allocates two device windows of
+ * n_channels x T_in samples and two staging buffers of n_channels x S, creates
+ * its own non-blocking copy stream, and builds the plan's forward tables.
+ *   DD_EINVAL  NULL argument, unknown dtype
+ *   DD_ENOMEM / DD_EHIP  allocation or stream set-up failed */
+typedef struct dd_realtime dd_realtime;
+int dd_realtime_create(dd_realtime **out, const dd_plan *plan, dd_dtype in_type, void *stream);
+
+/* Append one chunk and dedisperse the window.
+ *   h_chunk     host memory, n_channels rows of n_samples samples of the bound
+ *               in_type, row stride h_stride >= n_samples elements.  The copy to
+ *               the device runs asynchronously on the object's copy stream
+ *               (overlapping the previous chunk's kernels when h_chunk is pinned,
+ *               e.g. from hipHostMalloc); h_chunk must stay unchanged until the
+ *               next push on this object returns or the bound stream has been
+ *               synchronised.
+ *   d_out       device, [n_dm][out_stride] float32, out_stride >= n_samples;
+ *               written on the bound stream (columns [0, n_samples) only).
+ * The call blocks only until the previous chunk's host copy has completed.
+ * Must be called with the object's device current; pushes on one object from
+ * several host threads must be serialised by the caller.
+ *   DD_EINVAL  NULL argument or wrong device;  DD_ESHAPE  stride or alignment */
+int dd_realtime_push(dd_realtime *rt, const void *h_chunk, int64_t h_stride, float *d_out, int64_t out_stride);
+
+/* Number of chunks pushed so far (the next push is chunk *n_pushed). */
+int dd_realtime_pushed(const dd_realtime *rt, int64_t *n_pushed);
+
+/* Waits for the object's outstanding copies and kernels (and the bound
+ * stream, if anything was pushed), then frees it.  NULL is accepted. */
+int dd_realtime_destroy(dd_realtime *rt);
+
 /* ---------------------------------------------------------------- errors */
 
 /* Message for the calling thread's last failure ("" if none). */

@@ -10,6 +10,7 @@ there is no CPU fallback.
     y = dedisperse(x, plan)                 # x: [C][>= plan.input_samples] f32/f16/u8 on GPU
     y = Dedisperse.apply(x, plan)           # differentiable (adjoint in backward)
     Batch([plan_a, plan_b, ...]).run([xa, xb, ...])
+    rt = Realtime(plan, torch.uint8); y = rt.push(chunk)   # chunk: host [C][n_samples]
 """
 from __future__ import annotations
 
@@ -21,7 +22,7 @@ import numpy as np
 from . import _lib
 from ._lib import DD_ADJOINT, DD_F16, DD_F32, DD_FORWARD, DD_U8, DedispError, check  # noqa: F401
 
-__all__ = ["Plan", "Batch", "Dedisperse", "dedisperse", "dedisperse_adjoint", "DedispError",
+__all__ = ["Plan", "Batch", "Realtime", "Dedisperse", "dedisperse", "dedisperse_adjoint", "DedispError",
            "tile_variants", "DD_F32", "DD_F16", "DD_U8", "DD_FORWARD", "DD_ADJOINT"]
 
 
@@ -264,6 +265,71 @@ class Batch:
         if getattr(self, "_h", None) and self._h.value:
             _lib.lib().dd_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Realtime:
+    """Streaming dedispersion of one beam (see dd_realtime_create).
+
+    Each push appends one host chunk of ``plan.n_samples`` samples per channel
+    and returns the dedispersed output for the ``n_samples`` output times that
+    end ``plan.max_delay`` samples before the newest input; ``t0`` of push k is
+    ``k * n_samples - max_delay`` in stream samples.  Work runs on the stream
+    current at construction; chunks in pinned host memory overlap their copy
+    with the previous chunk's kernels."""
+
+    def __init__(self, plan: Plan, dtype=None, device=None):
+        torch = _torch()
+        self.plan = plan
+        self.dtype = torch.float32 if dtype is None else dtype
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        self._stream = torch.cuda.current_stream(self.device)
+        self._held = None
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(_lib.lib().dd_realtime_create(ctypes.byref(h), plan.handle, _dtype_code(self.dtype),
+                                                ctypes.c_void_p(self._stream.cuda_stream)))
+        self._h = h
+
+    @property
+    def pushed(self) -> int:
+        n = ctypes.c_int64()
+        check(_lib.lib().dd_realtime_pushed(self._h, ctypes.byref(n)))
+        return n.value
+
+    def push(self, chunk, out=None):
+        """chunk: CPU tensor [n_channels][>= n_samples] (row stride >= n_samples,
+        unit column stride) of the bound dtype.  Returns out [n_dm][n_samples]."""
+        torch = _torch()
+        p = self.plan
+        if chunk.device.type != "cpu":
+            raise ValueError("chunks are host tensors")
+        if chunk.dtype != self.dtype:
+            raise TypeError("chunk dtype %s, object bound to %s" % (chunk.dtype, self.dtype))
+        if chunk.dim() != 2 or chunk.shape[0] != p.n_channels or chunk.shape[1] < p.n_samples or chunk.stride(1) != 1:
+            raise ValueError("chunk must be [n_channels][>= n_samples] with unit column stride")
+        if out is None:
+            out = torch.empty((p.n_dm, p.n_samples), dtype=torch.float32, device=self.device)
+        if out.dtype != torch.float32 or out.device != self.device or out.dim() != 2 or out.stride(1) != 1 \
+                or out.shape[0] != p.n_dm or out.shape[1] < p.n_samples:
+            raise ValueError("out must be float32 [n_dm][>= n_samples] on the object's device")
+        with torch.cuda.device(self.device):
+            check(_lib.lib().dd_realtime_push(self._h, ctypes.c_void_p(chunk.data_ptr()), chunk.stride(0),
+                                              ctypes.c_void_p(out.data_ptr()), out.stride(0)))
+        # The library reads the chunk asynchronously until the next push returns.
+        self._held = chunk
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.lib().dd_realtime_destroy(self._h)
+            self._h = ctypes.c_void_p()
+            self._held = None
 
     def __del__(self):
         try:

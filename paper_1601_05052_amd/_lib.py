@@ -48,6 +48,10 @@ SIGNATURES = {
     "dd_batch_adds": [vp, P(dbl)],
     "dd_batch_variants": [vp, P(i32)],
     "dd_batch_destroy": [vp],
+    "dd_realtime_create": [P(vp), vp, ctypes.c_int, vp],
+    "dd_realtime_push": [vp, vp, i64, vp, i64],
+    "dd_realtime_pushed": [vp, P(i64)],
+    "dd_realtime_destroy": [vp],
     "dd_last_error": [],
     "dd_version": [],
 }

@@ -146,6 +146,20 @@ def test_null_plan_queries():
     assert L.dd_batch_autotune(arr, 1, 9, 1, None, None) == _lib.DD_EINVAL    # dtype
 
 
+def test_realtime_rejects_bad_arguments_before_gpu_work():
+    L = _lib.lib()
+    p = Plan.from_setup(synth.TINY)
+    h = ctypes.c_void_p()
+    assert L.dd_realtime_create(None, p.handle, 0, None) == _lib.DD_EINVAL
+    assert L.dd_realtime_create(ctypes.byref(h), None, 0, None) == _lib.DD_EINVAL
+    assert L.dd_realtime_create(ctypes.byref(h), p.handle, 9, None) == _lib.DD_EINVAL
+    assert not h.value
+    assert L.dd_realtime_push(None, _fake(0x1000), p.n_samples, _fake(0x9000), p.n_samples) == _lib.DD_EINVAL
+    n = ctypes.c_int64()
+    assert L.dd_realtime_pushed(None, ctypes.byref(n)) == _lib.DD_EINVAL
+    assert L.dd_realtime_destroy(None) == _lib.DD_OK
+
+
 def test_tile_variants_cover_paper_parameters():
     """Sec. III-B: work-items and elements per work-item, in time and in DM."""
     vs = tile_variants()

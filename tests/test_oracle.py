@@ -122,3 +122,25 @@ def test_oracle_rejects_bad_plans():
         oracle.delay_table(4, 1400.0, -1.0, 5e-5, 0.0, 0.5, 4)
     with pytest.raises(ValueError):
         oracle.delay_table(4, 10.0, 1.0, 1e-12, 0.0, 1e6, 4)   # delay beyond int32
+
+
+def test_stream_windows_tile_the_output():
+    """Streaming semantics (one chunk of S samples per step, Sec. III-A): the
+    dedispersion of the window of stream times [k*S - max_delay, (k+1)*S), with
+    zeros before time 0, is the slice [k*S - max_delay, k*S - max_delay + S) of
+    the dedispersion of the whole zero-padded stream, for chunks shorter and
+    longer than the largest delay."""
+    for S in (4096, 100):
+        args = (64, 1400.0, 1.5625, 5e-5, 0.0, 0.5, 128)
+        table = oracle.delay_table(*args)
+        M = int(table.max())
+        K = 3 if S > M else 9
+        x = synth.integers_f32(64, K * S, seed=7).astype(np.float64)
+        padded = np.concatenate([np.zeros((64, M)), x], axis=1)
+        full = oracle.dedisperse(padded, table, K * S)
+        for k in range(K):
+            w = padded[:, k * S:k * S + S + M]
+            assert np.array_equal(oracle.dedisperse(w, table, S), full[:, k * S:(k + 1) * S])
+        # stream time -max_delay reads channel ch at stream time delay - max_delay
+        ch = np.arange(64)
+        assert np.array_equal(full[:, 0], np.array([padded[ch, table[i]].sum() for i in range(128)]))
