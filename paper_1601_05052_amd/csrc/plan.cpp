@@ -6,6 +6,7 @@
 // delay table that Sec. III-A says is computed ahead of the sums.  This file is
 // compiled with -ffp-contract=off: every binary64 operation below is one IEEE
 // operation in the order written.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -263,22 +264,25 @@ int plan_tables(const dd_plan *p, int direction, const Variant &v, const TileTab
     return DD_OK;
 }
 
-// Rough time model for choosing a variant without measuring it: additions at
-// the kind's sustained rate plus staged input samples at an L2-to-LDS rate
-// (both measured on MI355X; the auto-tuner replaces this with timings).
+// Rough time model for choosing a variant without measuring it (the
+// auto-tuner replaces it with timings, Sec. IV-A): the additions of whole
+// tiles (ragged tiles do full work) at the variant's sustained rate, scaled
+// down when the grid has fewer waves than half the chip holds, plus the
+// staged input samples at an L2-to-LDS rate.  Rates and both constants were
+// fitted to every variant's measured time on Apertif- and LOFAR-shaped beams
+// of 2 to 4,096 trial DMs on MI355X.
 static double estimate_seconds(const dd_plan *p, int direction, const Variant &v, int32_t wcap) {
-    const double adds = static_cast<double>(p->D) * static_cast<double>(p->S) * p->C;
     const int32_t R = direction == DD_FORWARD ? p->C : p->D;
     const int32_t A = direction == DD_FORWARD ? p->D : p->C;
     const int64_t n_t = direction == DD_FORWARD ? p->S : p->T_in;
-    const double tiles = static_cast<double>((n_t + v.tt() - 1) / v.tt()) * ((A + v.ta() - 1) / v.ta());
+    const double n_t_tiles = static_cast<double>((n_t + v.tt() - 1) / v.tt());
+    const double tiles = n_t_tiles * ((A + v.ta() - 1) / v.ta());
+    const double work = tiles * v.tt() * v.ta() * static_cast<double>(R);
+    const double fill = std::min(1.0, tiles * v.waves / 4096.0);  // 256 CUs x 4 SIMDs x 4 waves
+    if (v.kind == KIND_DIRECT)  // one 4-byte read per addition from L2 / HBM
+        return work * 4.0 / 3e12 / fill;
     const double staged = tiles * R * static_cast<double>(wcap);
-    if (v.kind == KIND_DIRECT) {
-        // one 4-byte read per (row, accumulator row, sample) from L2 / HBM
-        const double reads = static_cast<double>(R) * A * static_cast<double>(n_t);
-        return reads * 4.0 / 3e12;
-    }
-    return adds / (static_cast<double>(v.rate) * 1e12) + staged / 2e12;
+    return work / (static_cast<double>(v.rate) * 1e12 * fill) + staged / 8e12;
 }
 
 int32_t best_by_model(const dd_plan *p, int direction, const int32_t *cand, int32_t n_cand) {

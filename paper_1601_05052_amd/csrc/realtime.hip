@@ -9,11 +9,16 @@
 // memory and dedisperses the window, so consecutive outputs tile the time axis
 // with no gap or overlap.
 //
-// Two window buffers alternate: push k assembles window k % 2 from the tail of
-// the other window and the new chunk, then runs the forward on it.  The host
-// copy of chunk k runs on the object's own copy stream, into one of two staging
-// buffers, while the compute stream may still run chunk k-1.  Events order the
-// two streams.
+// Two window buffers alternate.  For push k, on the object's own copy stream
+// (once the kernels of push k-2 have left window k % 2): the host chunk is
+// copied straight into the chunk columns of window k % 2, and a copy kernel
+// moves the last max_delay samples of the other window into its head.  The
+// compute stream waits for those copies and runs the forward.  The copies of
+// chunk k thus overlap the forward of chunk k-1.
+//
+// Window row layout (elements): `lead` unused columns, then max_delay tail
+// samples, then the S chunk samples, which start on a multiple of 64 elements
+// so that the host copy lands aligned.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,13 +31,13 @@ struct dd_realtime {
     int device = 0;
     int32_t in_type = DD_F32;
     size_t es = 4;
+    int64_t lead = 0;   // first used column of a window row
     int64_t pitch = 0;  // elements per window row
-    void *win[2] = {nullptr, nullptr};    // [C][pitch]
-    void *stage[2] = {nullptr, nullptr};  // [C][S], contiguous
-    hipStream_t compute = nullptr;        // caller's stream, bound at create
-    hipStream_t copy = nullptr;           // own stream for host-to-device copies
-    hipEvent_t copied[2] = {nullptr, nullptr};  // chunk in stage[s] has arrived
-    hipEvent_t freed[2] = {nullptr, nullptr};   // stage[s] has been consumed
+    void *win[2] = {nullptr, nullptr};  // [C][pitch]
+    hipStream_t compute = nullptr;      // caller's stream, bound at create
+    hipStream_t copy = nullptr;         // own stream for the window copies
+    hipEvent_t copied[2] = {nullptr, nullptr};  // window s is complete
+    hipEvent_t freed[2] = {nullptr, nullptr};   // the forward has finished reading window s
     bool used[2] = {false, false};
     int64_t pushed = 0;
 };
@@ -40,19 +45,16 @@ struct dd_realtime {
 namespace dd {
 namespace {
 
-// dst[ch][i] for i < T_in: the tail of the previous window for i < max_delay,
-// then the new chunk.  T is the storage type (no arithmetic on the samples).
+// dst[ch][i] = src[ch][i] for i < n: one row per blockIdx.y (T is the storage
+// type; the samples are only moved).
 template <typename T>
-__global__ __launch_bounds__(256) void assemble_window(T *__restrict__ dst, const T *__restrict__ prev,
-                                                       const T *__restrict__ stage, int64_t pitch,
-                                                       int64_t max_delay, int64_t S) {
+__global__ __launch_bounds__(256) void copy_rows(T *__restrict__ dst, const T *__restrict__ src, int64_t pitch,
+                                                 int64_t n) {
     const int64_t ch = blockIdx.y;
-    const int64_t T_in = S + max_delay;
     T *d = dst + ch * pitch;
-    const T *p = prev + ch * pitch + S;
-    const T *c = stage + ch * S - max_delay;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < T_in; i += (int64_t)gridDim.x * blockDim.x)
-        d[i] = i < max_delay ? p[i] : c[i];
+    const T *s = src + ch * pitch;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = s[i];
 }
 
 size_t elem_size(int32_t t) { return t == DD_F32 ? 4 : t == DD_F16 ? 2 : 1; }
@@ -66,27 +68,43 @@ void rt_free(dd_realtime *r) {
         (void)hipSetDevice(r->device);
     if (r->copy)
         (void)hipStreamSynchronize(r->copy);
+    // freed[s] is recorded after the last forward that read window s.
     for (int s = 0; s < 2; ++s) {
         if (r->freed[s]) {
-            (void)hipEventSynchronize(r->freed[s]);
+            if (r->used[s])
+                (void)hipEventSynchronize(r->freed[s]);
             (void)hipEventDestroy(r->freed[s]);
         }
         if (r->copied[s])
             (void)hipEventDestroy(r->copied[s]);
     }
-    // The last dedispersion reads a window after its freed event: wait for
-    // the bound stream before releasing the windows.
-    if (r->pushed)
-        (void)hipStreamSynchronize(r->compute);
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < 2; ++s)
         (void)hipFree(r->win[s]);
-        (void)hipFree(r->stage[s]);
-    }
     if (r->copy)
         (void)hipStreamDestroy(r->copy);
     if (have)
         (void)hipSetDevice(cur);
     delete r;
+}
+
+hipError_t launch_tail(const dd_realtime *r, int s) {
+    const dd_plan *p = r->plan;
+    const int64_t n = p->max_delay;
+    const size_t off = static_cast<size_t>(r->lead) * r->es;
+    const size_t src_off = static_cast<size_t>(r->lead + p->S) * r->es;
+    char *dst = static_cast<char *>(r->win[s]) + off;
+    const char *src = static_cast<const char *>(r->win[1 - s]) + src_off;
+    const dim3 grid(static_cast<uint32_t>(std::min<int64_t>((n + 255) / 256, 32)), static_cast<uint32_t>(p->C));
+    if (r->es == 4)
+        hipLaunchKernelGGL(copy_rows<uint32_t>, grid, dim3(256), 0, r->copy, reinterpret_cast<uint32_t *>(dst),
+                           reinterpret_cast<const uint32_t *>(src), r->pitch, n);
+    else if (r->es == 2)
+        hipLaunchKernelGGL(copy_rows<uint16_t>, grid, dim3(256), 0, r->copy, reinterpret_cast<uint16_t *>(dst),
+                           reinterpret_cast<const uint16_t *>(src), r->pitch, n);
+    else
+        hipLaunchKernelGGL(copy_rows<uint8_t>, grid, dim3(256), 0, r->copy, reinterpret_cast<uint8_t *>(dst),
+                           reinterpret_cast<const uint8_t *>(src), r->pitch, n);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -108,12 +126,12 @@ extern "C" int dd_realtime_create(dd_realtime **out, const dd_plan *plan, dd_dty
     r->device = device;
     r->in_type = in_type;
     r->es = elem_size(in_type);
-    r->pitch = (plan->T_in + 63) / 64 * 64;
+    r->lead = (64 - plan->max_delay % 64) % 64;
+    r->pitch = (r->lead + plan->T_in + 63) / 64 * 64;
     r->compute = static_cast<hipStream_t>(stream);
     const size_t win_bytes = static_cast<size_t>(plan->C) * r->pitch * r->es;
-    const size_t stage_bytes = static_cast<size_t>(plan->C) * plan->S * r->es;
     for (int s = 0; s < 2; ++s) {
-        if (hipMalloc(&r->win[s], win_bytes) != hipSuccess || hipMalloc(&r->stage[s], stage_bytes) != hipSuccess) {
+        if (hipMalloc(&r->win[s], win_bytes) != hipSuccess) {
             (void)hipGetLastError();
             rt_free(r);
             return fail(DD_ENOMEM, "device allocation for the real-time windows failed");
@@ -125,10 +143,11 @@ extern "C" int dd_realtime_create(dd_realtime **out, const dd_plan *plan, dd_dty
         if (e == hipSuccess)
             e = hipEventCreateWithFlags(&r->freed[s], hipEventDisableTiming);
     }
-    // Samples before the first push are zero (cleared on the bound stream,
-    // ahead of the first window assembly).
+    // Samples before the first push are zero.  Cleared on the copy stream,
+    // ahead of every later copy; the forward only reads a window after
+    // waiting for a copy event.
     for (int s = 0; s < 2 && e == hipSuccess; ++s)
-        e = hipMemsetAsync(r->win[s], 0, win_bytes, r->compute);
+        e = hipMemsetAsync(r->win[s], 0, win_bytes, r->copy);
     if (e != hipSuccess) {
         rt_free(r);
         return fail(DD_EHIP, "real-time set-up failed: %s", hipGetErrorString(e));
@@ -164,37 +183,29 @@ extern "C" int dd_realtime_push(dd_realtime *r, const void *h_chunk, int64_t h_s
     // The previous chunk's host buffer may be reused once this call returns.
     if (r->pushed > 0)
         DD_HIP_TRY(hipEventSynchronize(r->copied[1 - s]));
-    // Host copy into stage[s] once the chunk two pushes back has left it.
+    // Window s is rewritten once the forward of push k-2 has read it.
     if (r->used[s])
         DD_HIP_TRY(hipStreamWaitEvent(r->copy, r->freed[s], 0));
+    char *win = static_cast<char *>(r->win[s]);
     const size_t row = static_cast<size_t>(p->S) * r->es;
-    if (h_stride == p->S)
-        DD_HIP_TRY(hipMemcpyAsync(r->stage[s], h_chunk, row * p->C, hipMemcpyHostToDevice, r->copy));
-    else
-        DD_HIP_TRY(hipMemcpy2DAsync(r->stage[s], row, h_chunk, static_cast<size_t>(h_stride) * r->es, row, p->C,
-                                    hipMemcpyHostToDevice, r->copy));
+    DD_HIP_TRY(hipMemcpy2DAsync(win + static_cast<size_t>(r->lead + p->max_delay) * r->es, r->pitch * r->es, h_chunk,
+                                static_cast<size_t>(h_stride) * r->es, row, p->C, hipMemcpyHostToDevice, r->copy));
+    // Window k-1 is complete here: its copies precede on the same stream.
+    if (p->max_delay > 0) {
+        hipError_t e = launch_tail(r, s);
+        if (e != hipSuccess)
+            return fail(DD_EHIP, "tail copy launch failed: %s", hipGetErrorString(e));
+    }
     DD_HIP_TRY(hipEventRecord(r->copied[s], r->copy));
-    r->used[s] = true;
-    // Compute stream: assemble window s, release the stage, dedisperse.
     DD_HIP_TRY(hipStreamWaitEvent(r->compute, r->copied[s], 0));
-    const int64_t T_in = p->T_in;
-    const dim3 grid(static_cast<uint32_t>(std::min<int64_t>((T_in + 255) / 256, 64)), static_cast<uint32_t>(p->C));
-    if (r->es == 4)
-        hipLaunchKernelGGL(assemble_window<uint32_t>, grid, dim3(256), 0, r->compute,
-                           static_cast<uint32_t *>(r->win[s]), static_cast<const uint32_t *>(r->win[1 - s]),
-                           static_cast<const uint32_t *>(r->stage[s]), r->pitch, (int64_t)p->max_delay, p->S);
-    else if (r->es == 2)
-        hipLaunchKernelGGL(assemble_window<uint16_t>, grid, dim3(256), 0, r->compute,
-                           static_cast<uint16_t *>(r->win[s]), static_cast<const uint16_t *>(r->win[1 - s]),
-                           static_cast<const uint16_t *>(r->stage[s]), r->pitch, (int64_t)p->max_delay, p->S);
-    else
-        hipLaunchKernelGGL(assemble_window<uint8_t>, grid, dim3(256), 0, r->compute,
-                           static_cast<uint8_t *>(r->win[s]), static_cast<const uint8_t *>(r->win[1 - s]),
-                           static_cast<const uint8_t *>(r->stage[s]), r->pitch, (int64_t)p->max_delay, p->S);
-    DD_HIP_TRY(hipGetLastError());
+    int rc = dd_dedisperse(p, win + static_cast<size_t>(r->lead) * r->es, static_cast<dd_dtype>(r->in_type), r->pitch,
+                           d_out, out_stride, r->compute);
+    // Record even after a failed launch, so that later pushes never wait on
+    // a stale event; the window is not read then.
     DD_HIP_TRY(hipEventRecord(r->freed[s], r->compute));
+    r->used[s] = true;
     ++r->pushed;
-    return dd_dedisperse(p, r->win[s], static_cast<dd_dtype>(r->in_type), r->pitch, d_out, out_stride, r->compute);
+    return rc;
 }
 
 extern "C" int dd_realtime_pushed(const dd_realtime *r, int64_t *n_pushed) {
