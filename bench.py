@@ -42,8 +42,9 @@ ADD_PEAK_TFLOPS = 256 * 128 * 2.4e9 / 1e12
 
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ["paper_1601_05052_amd/csrc/" + n for n in (
-    "srs_regwin.h", "regwin_asm.h", "srs_tile.h", "srs_launch.h", "srs_variants.def", "srs_inst.inc",
-    "srs_kernels_f32.hip", "variants.cpp", "plan.cpp")]
+    "srs_regwin.h", "regwin_asm.h", "srs_tile.h", "srs_launch.h", "srs_inst.inc", "srs_kernels_f32.hip",
+    "variants.cpp", "plan.cpp")]
+VARIANT_LIST = "paper_1601_05052_amd/csrc/srs_variants.def"
 
 
 def log(msg):
@@ -51,22 +52,29 @@ def log(msg):
 
 
 def kernel_source_hash():
-    """Hash of the sources that determine the kernels' code.  The variant
-    list enters without its cost-model rates and comments, which do not."""
+    """Hash of the sources that determine the kernels' code and tables (the
+    variant list enters per variant, see variant_entry)."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as f:
-            data = f.read()
-        if rel.endswith(".def"):
-            text = re.sub(r"/\*.*?\*/|//[^\n]*", "", data.decode(), flags=re.S)
-            data = re.sub(r"\s+", " ", re.sub(r",\s*[0-9.]+f\)", ")", text)).encode()
-        h.update(data)
+            h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def variant_entry(variant):
+    """The variant's entry in the variant list, without its cost-model rate and
+    comments (which do not change its code); None if there is no such entry."""
+    with open(os.path.join(ROOT, VARIANT_LIST)) as f:
+        text = re.sub(r"/\*.*?\*/|//[^\n]*", "", f.read(), flags=re.S)
+    for m in re.finditer(r"X_\w+\(\s*(\d+)\s*,[^)]*\)", text):
+        if int(m.group(1)) == variant:
+            return re.sub(r"\s+", "", re.sub(r",\s*[0-9.]+f\)", ")", m.group(0)))
+    return None
 
 
 def measured_traffic(workload, variant):
     """HBM-side bytes per launch from the committed counter summary, only if it
-    was taken on the current kernel sources and the same tile variant."""
+    was taken on the current kernel sources and the same variant entry."""
     path = os.path.join(PROFILES, "traffic_%s_fwd.json" % workload)
     try:
         with open(path) as f:
@@ -75,9 +83,10 @@ def measured_traffic(workload, variant):
         return None
     if t.get("source_hash") != kernel_source_hash():
         return None
-    if t.get("variant") == variant:
-        return t.get("traffic_bytes")
-    return t.get("by_variant", {}).get(str(variant))
+    rec = t.get("by_variant", {}).get(str(variant))
+    if not rec or rec.get("entry") != variant_entry(variant):
+        return None
+    return rec.get("bytes")
 
 
 def compulsory_bytes(setup, in_bytes_per_sample, plan):
