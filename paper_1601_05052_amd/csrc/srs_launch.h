@@ -61,13 +61,14 @@ __global__ void __launch_bounds__(64 * NW)
                                                     lds_p);
 }
 
-template <typename TIn, int IT, int NW, int U>
+template <typename TIn, int IT, int NW, int U, bool CARRY>
 __global__ void __launch_bounds__(64 * NW)
     srs_direct_kernel(const TIn *__restrict__ in, float *__restrict__ out, const int32_t *__restrict__ rel,
-                      const int32_t *__restrict__ base, SrsDims d) {
+                      const int32_t *__restrict__ base, SrsDims d, int32_t r_begin, int32_t r_end) {
     int32_t tile_t, tile_a;
     dev::tile_of_block(d, tile_t, tile_a);
-    dev::srs_tile_direct<TIn, IT, NW, U>(in, out, dev::as_ctab(rel), dev::as_ctab(base), d, tile_t, tile_a);
+    dev::srs_tile_direct<TIn, IT, NW, U, CARRY>(in, out, dev::as_ctab(rel), dev::as_ctab(base), d, tile_t, tile_a,
+                                                r_begin, r_end);
 }
 
 // Multi-beam forms: work-group g takes items[g] = (beam << 24) | logical tile
@@ -161,8 +162,8 @@ __global__ void __launch_bounds__(64 * NW)
     BeamTile bt;
     if (!beam_tile(ptrs, descs, items, bt))
         return;
-    dev::srs_tile_direct<TIn, IT, NW, U>(static_cast<const TIn *>(bt.in), bt.out, bt.rel, bt.base,
-                                         bt.d, bt.tile_t, bt.tile_a);
+    dev::srs_tile_direct<TIn, IT, NW, U, false>(static_cast<const TIn *>(bt.in), bt.out, bt.rel, bt.base,
+                                                bt.d, bt.tile_t, bt.tile_a, 0, bt.d.n_rows);
 }
 
 inline hipError_t set_lds_limit(const void *fn, size_t lds) {
@@ -204,11 +205,21 @@ hipError_t launch_ldsp(const SrsArgs &a, const SrsDims &d, uint32_t blocks, size
     return hipGetLastError();
 }
 
-template <typename TIn, int IT, int NW, int U>
+// RB > 0: the rows are summed in blocks of RB by successive launches, each
+// continuing the partial sums the previous one left in the output (the
+// kernel boundary keeps every work-group within one block of rows).
+template <typename TIn, int IT, int NW, int U, int RB>
 hipError_t launch_direct(const SrsArgs &a, const SrsDims &d, uint32_t blocks, size_t, hipStream_t s) {
-    hipLaunchKernelGGL((srs_direct_kernel<TIn, IT, NW, U>), dim3(blocks), dim3(64 * NW), 0, s,
-                       static_cast<const TIn *>(a.in), a.out, a.rel, a.base, d);
-    return hipGetLastError();
+    const int32_t step = RB > 0 ? RB : d.n_rows;
+    for (int32_t r0 = 0; r0 < d.n_rows; r0 += step) {
+        const int32_t r1 = d.n_rows - r0 > step ? r0 + step : d.n_rows;
+        hipLaunchKernelGGL((srs_direct_kernel<TIn, IT, NW, U, (RB > 0)>), dim3(blocks), dim3(64 * NW), 0, s,
+                           static_cast<const TIn *>(a.in), a.out, a.rel, a.base, d, r0, r1);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace kern

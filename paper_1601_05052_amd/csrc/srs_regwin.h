@@ -482,26 +482,48 @@ __device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float 
 // delays differ by thousands of samples): each wave owns one accumulator row
 // and reads every operand straight from memory with bounds-checked buffer
 // loads (lane l: samples t0 + l + 64j, coalesced), U input rows in flight.
-template <typename TIn, int IT, int NW, int U>
+//
+// Rows [r_begin, r_end) are summed.  With CARRY the sums continue the
+// partial sums already in `out` (a previous launch's rows), so the rows can
+// be split over successive launches with the same result, and the time tiles
+// of each accumulator tile are rotated by the offset of the block's middle
+// row: at that row every accumulator tile of a contiguous run of logical
+// tiles (one XCD's share) reads the same input samples, rather than samples
+// up to the largest delay apart, so their reads share the XCD's L2.  A
+// rotation of the time tiles: every tile is still computed exactly once.
+template <typename TIn, int IT, int NW, int U, bool CARRY>
 __device__ __forceinline__ void srs_tile_direct(const TIn *__restrict__ in, float *__restrict__ out,
                                                 ctab *__restrict__ rel, ctab *__restrict__ base, const SrsDims &d,
-                                                int32_t tile_t, int32_t tile_a) {
+                                                int32_t tile_t, int32_t tile_a, int32_t r_begin, int32_t r_end) {
     constexpr int TT = 64 * IT;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t t0 = static_cast<int64_t>(tile_t) * TT;
     ctab *base_tile = base + static_cast<int64_t>(tile_a) * d.n_rows;
     ctab *rel_tile = rel + static_cast<int64_t>(tile_a) * d.n_rows * NW + wave;
+    if constexpr (CARRY) {
+        const int32_t mid = __builtin_amdgcn_readfirstlane(base_tile[r_begin + (r_end - r_begin) / 2]);
+        const int32_t shift = (mid >= 0 ? mid / TT : -((-mid + TT - 1) / TT)) % d.n_t_tiles;  // (-n, n)
+        tile_t -= shift;
+        if (tile_t < 0)
+            tile_t += d.n_t_tiles;
+        else if (tile_t >= d.n_t_tiles)
+            tile_t -= d.n_t_tiles;
+    }
+    const int64_t t0 = static_cast<int64_t>(tile_t) * TT;
     const int32_t n_bytes = static_cast<int32_t>(d.in_valid * static_cast<int64_t>(sizeof(TIn)));
+    const int32_t ag = tile_a * NW + wave;
+    float *dst = out + static_cast<int64_t>(min(ag, d.n_acc - 1)) * d.out_stride;
     float acc[IT];
 #pragma unroll
-    for (int j = 0; j < IT; ++j)
-        acc[j] = 0.f;
-    for (int32_t r0 = 0; r0 < d.n_rows; r0 += U) {
+    for (int j = 0; j < IT; ++j) {
+        const int64_t t = t0 + lane + 64 * j;
+        acc[j] = (CARRY && r_begin > 0 && ag < d.n_acc && t < d.n_t) ? dst[t] : 0.f;
+    }
+    for (int32_t r0 = r_begin; r0 < r_end; r0 += U) {
         float v[U][IT];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int32_t r = min(r0 + u, d.n_rows - 1);
+            const int32_t r = min(r0 + u, r_end - 1);
             const int64_t g0 = t0 + __builtin_amdgcn_readfirstlane(base_tile[r]) +
                                __builtin_amdgcn_readfirstlane(rel_tile[static_cast<int64_t>(r) * NW]);
             const TIn *rp = in + static_cast<int64_t>(r) * d.in_stride;
@@ -511,7 +533,7 @@ __device__ __forceinline__ void srs_tile_direct(const TIn *__restrict__ in, floa
             for (int j = 0; j < IT; ++j) {
                 const int64_t g = g0 + lane + 64 * j;
                 const uint32_t off = g >= 0 ? static_cast<uint32_t>(g) * sizeof(TIn) : kOutOfRange;
-                v[u][j] = (r0 + u < d.n_rows) ? buffer_ld<TIn>(rs, off) : 0.f;
+                v[u][j] = (r0 + u < r_end) ? buffer_ld<TIn>(rs, off) : 0.f;
             }
         }
 #pragma unroll
@@ -520,14 +542,17 @@ __device__ __forceinline__ void srs_tile_direct(const TIn *__restrict__ in, floa
             for (int j = 0; j < IT; ++j)
                 acc[j] += v[u][j];
     }
-    const int32_t ag = tile_a * NW + wave;
     if (ag < d.n_acc) {
-        float *dst = out + static_cast<int64_t>(ag) * d.out_stride;
+        const bool last = !CARRY || r_end >= d.n_rows;  // the next launch re-reads partial sums
 #pragma unroll
         for (int j = 0; j < IT; ++j) {
             const int64_t t = t0 + lane + 64 * j;
-            if (t < d.n_t)
-                __builtin_nontemporal_store(acc[j], dst + t);
+            if (t < d.n_t) {
+                if (last)
+                    __builtin_nontemporal_store(acc[j], dst + t);
+                else
+                    dst[t] = acc[j];
+            }
         }
     }
 }
