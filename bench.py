@@ -208,6 +208,16 @@ def extras(torch, dd, stream, steps):
     r["hbm_GBps"] = r["compulsory_bytes"] / (r["ms"] * 1e-3) / 1e9
     res["lofar_f32"] = r
     log("lofar f32: %.3f ms %.1f GFLOP/s" % (r["ms"], r["gflops"]))
+    lp = dd.Plan.from_setup(synth.LOFAR)
+    lp.autotune(dd.DD_ADJOINT, dd.DD_F32, reps=3)
+    lp.prepare(dd.DD_ADJOINT, dd.DD_F32)
+    gy = torch.randn((synth.LOFAR.n_dm, synth.LOFAR.n_samples), device="cuda")
+    gx = torch.empty((synth.LOFAR.n_channels, lp.input_samples), device="cuda")
+    ms_la, _ = timed(torch, lambda: dd.dedisperse_adjoint(gy, lp, out=gx), steps, 2, stream)
+    res["lofar_adjoint"] = dict(ms=ms_la, gflops=synth.LOFAR.adds / (ms_la * 1e-3) / 1e9,
+                                tile=lp.get_tile(direction=dd.DD_ADJOINT))
+    log("lofar adjoint: %.3f ms (variant %d)" % (ms_la, res["lofar_adjoint"]["tile"]))
+    del gy, gx
     # low precision storage, Apertif
     for dt in ("u8", "f16"):
         r, _ = measure_forward(torch, dd, synth.APERTIF, dt, steps, 2, stream)

@@ -14,7 +14,7 @@ namespace dd {
 // auto-tuner replaces it with timings, Sec. IV-A): the additions of whole
 // tiles (ragged tiles do full work) at the variant's sustained rate, scaled
 // down when the grid has fewer waves than half the chip holds, plus the
-// staged input samples at an L2-to-LDS rate.  Rates and both constants were
+// staged input samples at an L2-to-LDS rate (the direct kind stages none).  Rates and both constants were
 // fitted to every variant's measured time on Apertif- and LOFAR-shaped beams
 // of 2 to 4,096 trial DMs on MI355X.
 static double estimate_seconds(const dd_plan *p, int direction, const Variant &v, int32_t wcap) {
@@ -25,8 +25,8 @@ static double estimate_seconds(const dd_plan *p, int direction, const Variant &v
     const double tiles = n_t_tiles * ((A + v.ta() - 1) / v.ta());
     const double work = tiles * v.tt() * v.ta() * static_cast<double>(R);
     const double fill = std::min(1.0, tiles * v.waves / 4096.0);  // 256 CUs x 4 SIMDs x 4 waves
-    if (v.kind == KIND_DIRECT)  // one 4-byte read per addition from L2 / HBM
-        return work * 4.0 / 3e12 / fill;
+    if (v.kind == KIND_DIRECT)  // one 4-byte read per addition from L2 / HBM, no staging
+        return work / (static_cast<double>(v.rate) * 1e12 * fill);
     const double staged = tiles * R * static_cast<double>(wcap);
     return work / (static_cast<double>(v.rate) * 1e12 * fill) + staged / 8e12;
 }
