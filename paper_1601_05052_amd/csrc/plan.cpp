@@ -89,6 +89,20 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
     int32_t max_spread = 0;
     int64_t need = 0;  // regwin: largest staged-row index a lane window touches, + 1
     bool ok = true;
+    // Row spans: per (accumulator tile, time tile), the rows [lo, hi) with at
+    // least one operand index t + O[r][a] inside [0, in_valid); the others add
+    // only zeros there.  Rows are kept when the hull of their operand indices
+    // meets the input, so the span is conservative.
+    const bool want_span = build && (v.kind == KIND_REGWIN || v.kind == KIND_DIRECT);
+    const int64_t n_t = direction == DD_FORWARD ? p->S : p->T_in;
+    const int64_t in_valid = direction == DD_FORWARD ? p->T_in : p->S;
+    const int32_t n_t_tiles = static_cast<int32_t>((n_t + TT - 1) / TT);
+    std::vector<int32_t> row_lo, row_hi;
+    if (want_span) {
+        L->span.assign(static_cast<size_t>(n_tiles) * n_t_tiles * 2, 0);
+        row_lo.resize(R);
+        row_hi.resize(R);
+    }
     for (int32_t k = 0; k < n_tiles && ok; ++k) {
         for (int32_t r = 0; r < R && ok; ++r) {
             int32_t lo = std::numeric_limits<int32_t>::max(), hi = std::numeric_limits<int32_t>::min();
@@ -100,6 +114,10 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
             max_spread = std::max(max_spread, hi - lo);
             if (build)
                 L->base[(size_t)k * R + r] = lo;
+            if (want_span) {
+                row_lo[r] = lo;
+                row_hi[r] = hi;
+            }
             if (v.kind != KIND_REGWIN) {
                 if (build)
                     for (int32_t j = 0; j < TA; ++j)
@@ -140,10 +158,33 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
                 }
             }
         }
+        if (want_span && ok) {
+            for (int32_t j = 0; j < n_t_tiles; ++j) {
+                const int64_t t_first = static_cast<int64_t>(j) * TT;
+                const int64_t t_last = std::min<int64_t>(n_t, t_first + TT) - 1;
+                int32_t first = R, last = -1;
+                for (int32_t r = 0; r < R; ++r) {
+                    if (t_first + row_lo[r] <= in_valid - 1 && t_last + row_hi[r] >= 0) {
+                        first = std::min(first, r);
+                        last = r;
+                    }
+                }
+                int32_t *sp = &L->span[((size_t)k * n_t_tiles + j) * 2];
+                sp[0] = last < 0 ? 0 : first;
+                sp[1] = last < 0 ? 0 : last + 1;
+            }
+        }
     }
     L->max_spread = max_spread;
     if (!ok)
         return;
+    // Spans that skip nothing (every forward plan: the input covers every
+    // operand) are dropped; the kernels then take all rows.
+    bool skips = false;
+    for (size_t i = 0; i < L->span.size() && !skips; i += 2)
+        skips = L->span[i] != 0 || L->span[i + 1] != R;
+    if (!skips)
+        L->span.clear();
     const int64_t lds_limit = 160 * 1024;
     if (v.kind == KIND_DIRECT) {
         L->wcap = 0;
@@ -217,6 +258,7 @@ static void free_tables(TileTables &t) {
     (void)hipFree(t.d_base);
     (void)hipFree(t.d_rel);
     (void)hipFree(t.d_recs);
+    (void)hipFree(t.d_span);
     t = TileTables();
 }
 
@@ -252,6 +294,8 @@ int plan_tables(const dd_plan *p, int direction, const Variant &v, const TileTab
         rc = upload(L.rel, &t.d_rel);
     if (rc == DD_OK)
         rc = upload(L.recs, &t.d_recs);
+    if (rc == DD_OK)
+        rc = upload(L.span, &t.d_span);
     if (rc != DD_OK) {
         free_tables(t);
         return rc;
@@ -288,6 +332,7 @@ int make_args(const dd_plan *p, int direction, const Variant &v, const void *in,
     a->rel = t->d_rel;
     a->base = t->d_base;
     a->recs = t->d_recs;
+    a->span = t->d_span;
     a->wcap = t->wcap;
     a->rows_per_chunk = t->rows_per_chunk;
     a->lds_bytes = t->lds_bytes;

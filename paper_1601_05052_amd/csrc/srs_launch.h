@@ -42,12 +42,12 @@ __global__ void __launch_bounds__(64 * NW)
 template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX, int OCC>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OCC)))
     srs_regwin_kernel(const TIn *__restrict__ in, float *__restrict__ out, const int32_t *__restrict__ base,
-                      const int32_t *__restrict__ recs, SrsDims d) {
+                      const int32_t *__restrict__ recs, const int32_t *__restrict__ span, SrsDims d) {
     extern __shared__ __attribute__((aligned(16))) float lds_rw[];
     int32_t tile_t, tile_a;
     dev::tile_of_block(d, tile_t, tile_a);
-    dev::srs_tile_regwin<TIn, IT, TDW, NWR, NW, RPW, KMAX>(in, out, dev::as_ctab(base), dev::as_ctab(recs), d,
-                                                           tile_t, tile_a, lds_rw);
+    dev::srs_tile_regwin<TIn, IT, TDW, NWR, NW, RPW, KMAX>(in, out, dev::as_ctab(base), dev::as_ctab(recs),
+                                                           dev::as_ctab(span), d, tile_t, tile_a, lds_rw);
 }
 
 template <typename TIn, int IT, int TDW, int NW, int RPW, int KMAX>
@@ -64,11 +64,12 @@ __global__ void __launch_bounds__(64 * NW)
 template <typename TIn, int IT, int NW, int U, bool CARRY>
 __global__ void __launch_bounds__(64 * NW)
     srs_direct_kernel(const TIn *__restrict__ in, float *__restrict__ out, const int32_t *__restrict__ rel,
-                      const int32_t *__restrict__ base, SrsDims d, int32_t r_begin, int32_t r_end) {
+                      const int32_t *__restrict__ base, const int32_t *__restrict__ span, SrsDims d, int32_t r_begin,
+                      int32_t r_end) {
     int32_t tile_t, tile_a;
     dev::tile_of_block(d, tile_t, tile_a);
-    dev::srs_tile_direct<TIn, IT, NW, U, CARRY>(in, out, dev::as_ctab(rel), dev::as_ctab(base), d, tile_t, tile_a,
-                                                r_begin, r_end);
+    dev::srs_tile_direct<TIn, IT, NW, U, CARRY>(in, out, dev::as_ctab(rel), dev::as_ctab(base), dev::as_ctab(span), d,
+                                                tile_t, tile_a, r_begin, r_end);
 }
 
 // Multi-beam forms: work-group g takes items[g] = (beam << 24) | logical tile
@@ -141,8 +142,8 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OC
     BeamTile bt;
     if (!beam_tile(ptrs, descs, items, bt))
         return;
-    dev::srs_tile_regwin<TIn, IT, TDW, NWR, NW, RPW, KMAX>(static_cast<const TIn *>(bt.in), bt.out, bt.base, bt.recs, bt.d,
-                                                           bt.tile_t, bt.tile_a, lds_mr);
+    dev::srs_tile_regwin<TIn, IT, TDW, NWR, NW, RPW, KMAX>(static_cast<const TIn *>(bt.in), bt.out, bt.base, bt.recs,
+                                                           nullptr, bt.d, bt.tile_t, bt.tile_a, lds_mr);
 }
 
 template <typename TIn, int IT, int TDW, int NW, int RPW, int KMAX>
@@ -162,7 +163,7 @@ __global__ void __launch_bounds__(64 * NW)
     BeamTile bt;
     if (!beam_tile(ptrs, descs, items, bt))
         return;
-    dev::srs_tile_direct<TIn, IT, NW, U, false>(static_cast<const TIn *>(bt.in), bt.out, bt.rel, bt.base,
+    dev::srs_tile_direct<TIn, IT, NW, U, false>(static_cast<const TIn *>(bt.in), bt.out, bt.rel, bt.base, nullptr,
                                                 bt.d, bt.tile_t, bt.tile_a, 0, bt.d.n_rows);
 }
 
@@ -190,7 +191,7 @@ hipError_t launch_regwin(const SrsArgs &a, const SrsDims &d, uint32_t blocks, si
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * NW), lds, s, static_cast<const TIn *>(a.in), a.out, a.base,
-                       a.recs, d);
+                       a.recs, a.span, d);
     return hipGetLastError();
 }
 
@@ -214,7 +215,7 @@ hipError_t launch_direct(const SrsArgs &a, const SrsDims &d, uint32_t blocks, si
     for (int32_t r0 = 0; r0 < d.n_rows; r0 += step) {
         const int32_t r1 = d.n_rows - r0 > step ? r0 + step : d.n_rows;
         hipLaunchKernelGGL((srs_direct_kernel<TIn, IT, NW, U, (RB > 0)>), dim3(blocks), dim3(64 * NW), 0, s,
-                           static_cast<const TIn *>(a.in), a.out, a.rel, a.base, d, r0, r1);
+                           static_cast<const TIn *>(a.in), a.out, a.rel, a.base, a.span, d, r0, r1);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;

@@ -235,7 +235,7 @@ __device__ __forceinline__ void store_acc(const typename RW::Acc &acc, float *__
 // row's additions run.
 template <typename TIn, int IT, int TDW, int NWR, int NW, int RPW, int KMAX>
 __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, float *__restrict__ out,
-                                                ctab *__restrict__ base, ctab *__restrict__ recs,
+                                                ctab *__restrict__ base, ctab *__restrict__ recs, ctab *span,
                                                 const SrsDims &d, int32_t tile_t, int32_t tile_a, float *lds) {
     using RW = RegWin<IT, TDW, NWR>;
     constexpr int TT = 64 * IT;
@@ -249,6 +249,14 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
     const int64_t t0 = static_cast<int64_t>(tile_t) * TT;
     const int32_t n_chunks = (d.n_rows + CR - 1) / CR;
     ctab *rec_tile = recs + (static_cast<int64_t>(tile_a) * NW + wave) * n_chunks * (CR * RD);
+    // Chunks [c_lo, c_hi) hold every row with an operand inside the input
+    // for this tile; the rest would add only zeros (span: null = all rows).
+    int32_t c_lo = 0, c_hi = n_chunks;
+    if (span) {
+        const int64_t k = 2 * (static_cast<int64_t>(tile_a) * d.n_t_tiles + tile_t);
+        c_lo = __builtin_amdgcn_readfirstlane(span[k]) / CR;
+        c_hi = (__builtin_amdgcn_readfirstlane(span[k + 1]) + CR - 1) / CR;
+    }
 
     typename RW::Acc acc;
 #pragma unroll
@@ -266,7 +274,7 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
     // the current group's first row.
     constexpr int G = CR / 2;
     static_assert(CR % 2 == 0, "two record groups per chunk");
-    const int32_t n_groups = n_chunks * 2;
+    const int32_t n_groups = c_hi * 2;
     uint32_t rs0[G * RD], rs1[G * RD];
     auto load_recs = [&](uint32_t (&r)[G * RD], int32_t g, int dep) {
         ctab *p = rec_tile + static_cast<int64_t>(g) * (G * RD) + dep;
@@ -275,13 +283,14 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
             r[i] = static_cast<uint32_t>(p[i]);
     };
 
-    st.fetch(0);
-    st.store(0, lds);
-    if (n_chunks > 1)
-        st.fetch(1);
-    load_recs(rs0, 0, 0);
-    __syncthreads();  // chunk 0 staged
-    for (int32_t c = 0; c < n_chunks; ++c) {
+    if (c_lo < c_hi) {  // uniform over the work-group
+    st.fetch(c_lo);
+    st.store(c_lo, lds + (c_lo & 1) * buf_dw);
+    if (c_lo + 1 < c_hi)
+        st.fetch(c_lo + 1);
+    load_recs(rs0, 2 * c_lo, 0);
+    __syncthreads();  // first chunk staged
+    for (int32_t c = c_lo; c < c_hi; ++c) {
         const int32_t r0 = c * CR;
         const int32_t nr = min(CR, d.n_rows - r0);
         const uint32_t chunk_rd = lane_rd + static_cast<uint32_t>((c & 1) * buf_dw) * 4u;
@@ -308,14 +317,15 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
                 load_recs(oth, g + 1, __builtin_amdgcn_readfirstlane(dep));
             RW::add(acc, w, o);
         }
-        if (c + 1 < n_chunks) {
+        if (c + 1 < c_hi) {
             // The other buffer was last read in chunk c-1, which every wave
             // finished before the previous barrier.
             st.store(c + 1, lds + ((c + 1) & 1) * buf_dw);
-            if (c + 2 < n_chunks)
+            if (c + 2 < c_hi)
                 st.fetch(c + 2);
             __syncthreads();  // chunk c+1 staged; chunk c consumed by every wave
         }
+    }
     }
     store_acc<RW, IT, TDW, TA>(acc, out, d, t0, tile_a, wave, lane);
 }
@@ -493,8 +503,9 @@ __device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float 
 // rotation of the time tiles: every tile is still computed exactly once.
 template <typename TIn, int IT, int NW, int U, bool CARRY>
 __device__ __forceinline__ void srs_tile_direct(const TIn *__restrict__ in, float *__restrict__ out,
-                                                ctab *__restrict__ rel, ctab *__restrict__ base, const SrsDims &d,
-                                                int32_t tile_t, int32_t tile_a, int32_t r_begin, int32_t r_end) {
+                                                ctab *__restrict__ rel, ctab *__restrict__ base, ctab *span,
+                                                const SrsDims &d, int32_t tile_t, int32_t tile_a, int32_t r_begin,
+                                                int32_t r_end) {
     constexpr int TT = 64 * IT;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -519,11 +530,18 @@ __device__ __forceinline__ void srs_tile_direct(const TIn *__restrict__ in, floa
         const int64_t t = t0 + lane + 64 * j;
         acc[j] = (CARRY && r_begin > 0 && ag < d.n_acc && t < d.n_t) ? dst[t] : 0.f;
     }
-    for (int32_t r0 = r_begin; r0 < r_end; r0 += U) {
+    // Rows outside [span lo, span hi) add only zeros to this tile.
+    int32_t r_from = r_begin, r_to = r_end;
+    if (span) {
+        const int64_t k = 2 * (static_cast<int64_t>(tile_a) * d.n_t_tiles + tile_t);
+        r_from = max(r_from, __builtin_amdgcn_readfirstlane(span[k]));
+        r_to = min(r_to, __builtin_amdgcn_readfirstlane(span[k + 1]));
+    }
+    for (int32_t r0 = r_from; r0 < r_to; r0 += U) {
         float v[U][IT];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int32_t r = min(r0 + u, r_end - 1);
+            const int32_t r = min(r0 + u, r_to - 1);
             const int64_t g0 = t0 + __builtin_amdgcn_readfirstlane(base_tile[r]) +
                                __builtin_amdgcn_readfirstlane(rel_tile[static_cast<int64_t>(r) * NW]);
             const TIn *rp = in + static_cast<int64_t>(r) * d.in_stride;
@@ -533,7 +551,7 @@ __device__ __forceinline__ void srs_tile_direct(const TIn *__restrict__ in, floa
             for (int j = 0; j < IT; ++j) {
                 const int64_t g = g0 + lane + 64 * j;
                 const uint32_t off = g >= 0 ? static_cast<uint32_t>(g) * sizeof(TIn) : kOutOfRange;
-                v[u][j] = (r0 + u < r_end) ? buffer_ld<TIn>(rs, off) : 0.f;
+                v[u][j] = (r0 + u < r_to) ? buffer_ld<TIn>(rs, off) : 0.f;
             }
         }
 #pragma unroll
