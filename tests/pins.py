@@ -226,3 +226,88 @@ def run_all(orc):
     for p in SMALL_PLANS:
         for chk in FORWARD_CHECKS + ADJOINT_CHECKS:
             chk(orc, p)
+
+
+# ---------------------------------------------------------------- candidate search
+#
+# The boxcar search over dedispersed rows (oracle.search) is pinned by closed
+# forms of noise-free rows, an invariance of its definition, its degenerate
+# case and explicit loops on tiny rows.
+
+def search_brute(y, n_widths):
+    """(max snr, t, w) by explicit loops over every width and start (tiny rows)."""
+    y = [float(v) for v in np.asarray(y, dtype=np.float64)]
+    S = len(y)
+    mu = math.fsum(y) / S
+    sigma = math.sqrt(math.fsum((v - mu) ** 2 for v in y) / S)
+    if sigma == 0.0:
+        return 0.0, 0, 1
+    best = (-math.inf, 0, 1)
+    w = 1
+    for _ in range(n_widths):
+        if w > S:
+            break
+        for t in range(S - w + 1):
+            s = math.fsum(y[t + i] - mu for i in range(w)) / (sigma * math.sqrt(w))
+            if s > best[0]:
+                best = (s, t, w)
+        w *= 2
+    return best
+
+
+def check_search_spike(search_row):
+    """A single spike of any height in S samples: the best boxcar is the spike
+    alone, with S/N sqrt(S - 1) (mean A/S, standard deviation A sqrt(S-1)/S)."""
+    for S, A, t0 in ((100, 3.0, 17), (4096, 250.0, 4000), (7, 1.0, 0)):
+        y = np.zeros(S)
+        y[t0] = A
+        snr, t, w = search_row(y, 7)
+        assert math.isclose(snr, math.sqrt(S - 1), rel_tol=1e-12), (S, snr)
+        assert (t, w) == (t0, 1), (t, w)
+
+
+def check_search_boxcar_pulse(search_row):
+    """A noise-free boxcar of width 8 and height A: the best window is the
+    pulse itself, S/N = 8 (A - mu) / (sigma sqrt(8))."""
+    S, A, t0 = 1000, 2.5, 311
+    y = np.zeros(S)
+    y[t0:t0 + 8] = A
+    mu = 8 * A / S
+    sigma = math.sqrt((8 * (A - mu) ** 2 + (S - 8) * mu ** 2) / S)
+    snr, t, w = search_row(y, 6)
+    assert math.isclose(snr, 8 * (A - mu) / (sigma * math.sqrt(8)), rel_tol=1e-12), snr
+    assert (t, w) == (t0, 8), (t, w)
+
+
+def check_search_affine_invariance(search_row, seed=0):
+    """S/N is unchanged when a row is scaled by a > 0 and shifted."""
+    rng = np.random.default_rng(seed)
+    y = rng.standard_normal(500)
+    y[200:204] += 3.0
+    base = search_row(y, 5)
+    for a, b in ((3.0, 0.0), (0.25, 1e3), (7.0, -40.0)):
+        got = search_row(a * y + b, 5)
+        assert math.isclose(got[0], base[0], rel_tol=1e-9), (a, b, got, base)
+        assert got[1:] == base[1:], (a, b, got, base)
+
+
+def check_search_constant_row(search_row):
+    """A constant row has no spread: S/N 0 at (0, 1) by definition."""
+    assert search_row(np.full(64, 5.0), 4) == (0.0, 0, 1)
+
+
+def check_search_brute(search_row, seed=0):
+    rng = np.random.default_rng(seed)
+    for S, nw in ((1, 3), (5, 4), (33, 6), (64, 7)):
+        y = rng.standard_normal(S)
+        got, ref = search_row(y, nw), search_brute(y, nw)
+        assert math.isclose(got[0], ref[0], rel_tol=1e-12, abs_tol=1e-12), (S, got, ref)
+        assert got[1:] == ref[1:], (S, got, ref)
+
+
+def run_search(search_row):
+    check_search_spike(search_row)
+    check_search_boxcar_pulse(search_row)
+    check_search_affine_invariance(search_row)
+    check_search_constant_row(search_row)
+    check_search_brute(search_row)

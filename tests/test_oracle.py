@@ -144,3 +144,10 @@ def test_stream_windows_tile_the_output():
         # stream time -max_delay reads channel ch at stream time delay - max_delay
         ch = np.arange(64)
         assert np.array_equal(full[:, 0], np.array([padded[ch, table[i]].sum() for i in range(128)]))
+
+
+def test_search_oracle_pins():
+    """Boxcar candidate search: closed forms of noise-free rows, affine
+    invariance, the constant row, explicit loops on tiny rows."""
+    from oracle import search
+    pins.run_search(search.search_row)

@@ -48,3 +48,35 @@ def test_mutant_is_caught(name, tmp_path):
     mutant = oracle.COracle(lib)
     with pytest.raises(AssertionError):
         pins.run_all(mutant)
+
+
+# Planted mistakes in copies of the search oracle (oracle/search.py).
+SEARCH_MUTANTS = {
+    "sample_std": ("return mu, np.sqrt(np.mean((y - mu) ** 2))",
+                   "return mu, np.sqrt(np.sum((y - mu) ** 2) / (len(y) - 1))"),
+    "no_mean_subtraction": ("c = np.concatenate([[0.0], np.cumsum(y - mu)])",
+                            "c = np.concatenate([[0.0], np.cumsum(y)])"),
+    "width_not_sqrt": ("s = (c[w:] - c[:-w]) / (sigma * np.sqrt(w))", "s = (c[w:] - c[:-w]) / (sigma * w)"),
+    "window_off_by_one": ("s = (c[w:] - c[:-w]) / (sigma * np.sqrt(w))",
+                          "s = (c[w:] - c[:-w]) / (sigma * np.sqrt(w)); s = np.roll(s, 1)"),
+    "widths_skip_one": ("return [1 << k for k in range(n_widths) if (1 << k) <= n_samples]",
+                        "return [1 << k for k in range(1, n_widths) if (1 << k) <= n_samples]"),
+}
+
+
+def test_unmutated_search_oracle_passes():
+    from oracle import search
+    pins.run_search(search.search_row)
+
+
+@pytest.mark.parametrize("name", sorted(SEARCH_MUTANTS))
+def test_search_mutant_is_caught(name):
+    import types
+    from oracle import search
+    old, new = SEARCH_MUTANTS[name]
+    src = open(search.__file__).read()
+    assert src.count(old) == 1, "mutation site not found exactly once"
+    mod = types.ModuleType("search_mutant")
+    exec(compile(src.replace(old, new), "search_mutant.py", "exec"), mod.__dict__)
+    with pytest.raises(AssertionError):
+        pins.run_search(mod.search_row)
