@@ -229,6 +229,14 @@ def extras(torch, dd, stream, steps):
         r, _ = measure_forward(torch, dd, z, "f32", steps, 2, stream)
         res[z.name] = r
         log("%s: %.3f ms %.1f GFLOP/s (variant %d)" % (z.name, r["ms"], r["gflops"], r["tile"]))
+    # candidate search over the dedispersed Apertif rows (boxcars of 1 .. 1,024 samples)
+    sp = dd.Plan.from_setup(synth.APERTIF)
+    sy = dd.dedisperse(gpu_input(torch, synth.APERTIF, sp.input_samples, "f32", synth.APERTIF.seed), sp)
+    ms_s, _ = timed(torch, lambda: dd.search_boxcar(sy, n_widths=11), steps, 2, stream)
+    res["search_apertif"] = dict(ms=ms_s, n_widths=11, rows_bytes=sy.numel() * 4,
+                                 rows_GBps=sy.numel() * 4 / (ms_s * 1e-3) / 1e9)
+    log("search apertif (11 widths): %.3f ms, %.0f GB/s of rows" % (ms_s, res["search_apertif"]["rows_GBps"]))
+    del sy
     # streaming: one Apertif beam fed second by second from pinned host memory
     res["realtime_apertif_u8"] = realtime(torch, dd, stream, max(10, steps // 2))
     # adjoint and fwd+bwd (8 Apertif-shaped beams through autograd)

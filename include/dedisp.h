@@ -255,6 +255,28 @@ int dd_realtime_pushed(const dd_realtime *rt, int64_t *n_pushed);
  * stream, if anything was pushed), then frees it.  NULL is accepted. */
 int dd_realtime_destroy(dd_realtime *rt);
 
+/* ---------------------------------------------------------------- candidate search */
+
+/* Boxcar single-pulse search over dedispersed rows.  The dedispersed
+ * time-series are searched for pulses afterwards (Sec. I); the paper does not
+ * define that step, so this is the plain definition: for each row y[0:S]
+ * (S = n_samples), with mu and sigma its mean and population standard
+ * deviation,
+ *     snr_w(t) = sum_{i < w} (y[t + i] - mu) / (sigma * sqrt(w))
+ * for w = 1, 2, 4, ..., 2^(n_widths - 1) (widths <= S) and 0 <= t <= S - w.
+ * Per row it writes the largest snr and one (t, w) reaching it (ties: smaller
+ * w, then smaller t); a row with sigma == 0 gives (0, 0, 1).  mu and sigma are
+ * accumulated in binary64, boxcar sums in binary32.
+ *   d_rows      device, [n_rows][row_stride] float32 (e.g. dd_dedisperse's
+ *               output), row_stride >= n_samples
+ *   n_widths    1 .. 12 (widths up to 2048 samples)
+ *   d_snr       device, n_rows float32;  d_t, d_width: device, n_rows int32
+ * Runs asynchronously on `stream` (one work-group per row).
+ *   DD_EINVAL  NULL pointer, n_rows < 1, n_samples outside [1, 2^31), n_widths
+ *   DD_ESHAPE  row_stride < n_samples, misaligned pointer */
+int dd_search_boxcar(const float *d_rows, int64_t row_stride, int32_t n_rows, int64_t n_samples, int32_t n_widths,
+                     float *d_snr, int32_t *d_t, int32_t *d_width, void *stream);
+
 /* ---------------------------------------------------------------- errors */
 
 /* Message for the calling thread's last failure ("" if none). */

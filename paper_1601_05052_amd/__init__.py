@@ -11,6 +11,7 @@ there is no CPU fallback.
     y = Dedisperse.apply(x, plan)           # differentiable (adjoint in backward)
     Batch([plan_a, plan_b, ...]).run([xa, xb, ...])
     rt = Realtime(plan, torch.uint8); y = rt.push(chunk)   # chunk: host [C][n_samples]
+    snr, t, w = search_boxcar(y, n_widths=11)               # best boxcar per DM row
 """
 from __future__ import annotations
 
@@ -22,7 +23,7 @@ import numpy as np
 from . import _lib
 from ._lib import DD_ADJOINT, DD_F16, DD_F32, DD_FORWARD, DD_U8, DedispError, check  # noqa: F401
 
-__all__ = ["Plan", "Batch", "Realtime", "Dedisperse", "dedisperse", "dedisperse_adjoint", "DedispError",
+__all__ = ["Plan", "Batch", "Realtime", "search_boxcar", "Dedisperse", "dedisperse", "dedisperse_adjoint", "DedispError",
            "tile_variants", "DD_F32", "DD_F16", "DD_U8", "DD_FORWARD", "DD_ADJOINT"]
 
 
@@ -336,3 +337,25 @@ class Realtime:
             self.close()
         except Exception:
             pass
+
+
+def search_boxcar(rows, n_samples: Optional[int] = None, n_widths: int = 11):
+    """Best boxcar S/N per row (see dd_search_boxcar): rows [n_rows][>= n_samples]
+    float32 on the GPU -> (snr float32 [n_rows], t int32 [n_rows], width int32 [n_rows])."""
+    torch = _torch()
+    if not isinstance(rows, torch.Tensor) or not rows.is_cuda or rows.dtype != torch.float32:
+        raise TypeError("rows must be a float32 GPU tensor")
+    if rows.dim() != 2 or rows.stride(1) != 1:
+        raise ValueError("rows must be 2-D with unit column stride")
+    S = rows.shape[1] if n_samples is None else int(n_samples)
+    if S > rows.shape[1]:
+        raise ValueError("n_samples exceeds the row length")
+    n = rows.shape[0]
+    snr = torch.empty(n, dtype=torch.float32, device=rows.device)
+    t = torch.empty(n, dtype=torch.int32, device=rows.device)
+    w = torch.empty(n, dtype=torch.int32, device=rows.device)
+    with torch.cuda.device(rows.device):
+        check(_lib.lib().dd_search_boxcar(ctypes.c_void_p(rows.data_ptr()), rows.stride(0), n, S, int(n_widths),
+                                          ctypes.c_void_p(snr.data_ptr()), ctypes.c_void_p(t.data_ptr()),
+                                          ctypes.c_void_p(w.data_ptr()), _stream_handle(rows.device)))
+    return snr, t, w

@@ -52,6 +52,7 @@ SIGNATURES = {
     "dd_realtime_push": [vp, vp, i64, vp, i64],
     "dd_realtime_pushed": [vp, P(i64)],
     "dd_realtime_destroy": [vp],
+    "dd_search_boxcar": [vp, i64, i32, i64, i32, vp, vp, vp, vp],
     "dd_last_error": [],
     "dd_version": [],
 }

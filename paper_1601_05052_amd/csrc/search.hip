@@ -1,0 +1,175 @@
+// Boxcar candidate search over dedispersed rows.
+//
+// The dedispersed time-series are analysed further to find pulses (Sec. I);
+// the paper does not define that step.  This is the plain single-pulse
+// search: per row y[0:S], with mu and sigma the row's mean and population
+// standard deviation,
+//     snr_w(t) = sum_{i < w} (y[t + i] - mu) / (sigma * sqrt(w)),
+// for widths w = 1, 2, 4, ..., 2^(n_widths - 1) (those <= S) and
+// 0 <= t <= S - w; the result is the largest snr with one (t, w) reaching it
+// (0 at (0, 1) when sigma is 0).
+//
+// One work-group per row.  Mean and standard deviation are accumulated in
+// binary64 (two passes over the row); the centred samples are formed in
+// binary64 and rounded to binary32, so the row's offset never enters the
+// binary32 boxcar sums.  Boxcars are built by doubling in LDS,
+// B_2w(t) = B_w(t) + B_w(t + w), over chunks of the row with a halo of the
+// widest boxcar: pairwise sums, one addition per sample and width.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "internal.h"
+
+namespace dd {
+namespace {
+
+constexpr int kSearchThreads = 256;
+constexpr int kChunk = 4096;         // boxcar starts owned per chunk
+constexpr int kMaxWidthsLog = 12;    // widths up to 2^11 = 2048 samples
+constexpr int kHalo = 1 << (kMaxWidthsLog - 1);
+constexpr int kExt = kChunk + kHalo;  // samples staged per chunk
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();  // red is reused between calls
+    if (lane == 0)
+        red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < kSearchThreads / 64; ++w)
+        s += red[w];
+    return s;
+}
+
+struct Cand {
+    float snr;
+    int32_t t;
+    int32_t w;
+};
+
+// a before b: larger snr, then smaller width, then earlier start.
+__device__ __forceinline__ bool better(const Cand &a, const Cand &b) {
+    if (a.snr != b.snr)
+        return a.snr > b.snr;
+    if (a.w != b.w)
+        return a.w < b.w;
+    return a.t < b.t;
+}
+
+__global__ __launch_bounds__(kSearchThreads) void boxcar_search_kernel(const float *__restrict__ rows,
+                                                                     int64_t row_stride, int64_t S, int32_t n_widths,
+                                                                     float *__restrict__ snr_out,
+                                                                     int32_t *__restrict__ t_out,
+                                                                     int32_t *__restrict__ w_out) {
+    __shared__ float box[kExt];
+    __shared__ double red[kSearchThreads / 64];
+    __shared__ Cand cred[kSearchThreads];
+    const int tid = threadIdx.x;
+    const float *y = rows + static_cast<int64_t>(blockIdx.x) * row_stride;
+
+    double s = 0.0;
+    for (int64_t i = tid; i < S; i += kSearchThreads)
+        s += static_cast<double>(y[i]);
+    const double mu = block_sum(s, red) / static_cast<double>(S);
+    double q = 0.0;
+    for (int64_t i = tid; i < S; i += kSearchThreads) {
+        const double c = static_cast<double>(y[i]) - mu;
+        q += c * c;
+    }
+    const double sigma = sqrt(block_sum(q, red) / static_cast<double>(S));
+
+    Cand best{-INFINITY, 0, 1};
+    if (sigma > 0.0) {
+        const float inv_sigma = static_cast<float>(1.0 / sigma);
+        int32_t wmax = 1;
+        while (2 * wmax <= S && (31 - __builtin_clz(2 * wmax)) < n_widths)
+            wmax *= 2;
+        for (int64_t c0 = 0; c0 < S; c0 += kChunk) {
+            __syncthreads();  // the previous chunk's boxcars are consumed
+            for (int i = tid; i < kExt; i += kSearchThreads) {
+                const int64_t g = c0 + i;
+                box[i] = g < S ? static_cast<float>(static_cast<double>(y[g]) - mu) : 0.f;
+            }
+            __syncthreads();
+            // box holds B_w(c0 + i) for i + w <= kExt; widths double per level.
+            for (int32_t w = 1;; w *= 2) {
+                const float scale = inv_sigma * rsqrtf(static_cast<float>(w));
+                for (int i = tid; i < kChunk; i += kSearchThreads) {
+                    const int64_t t = c0 + i;
+                    if (t + w <= S) {
+                        const Cand c{box[i] * scale, static_cast<int32_t>(t), w};
+                        if (better(c, best))
+                            best = c;
+                    }
+                }
+                if (w >= wmax)
+                    break;
+                // B_2w(i) = B_w(i) + B_w(i + w) for i + 2w <= kExt: read all,
+                // then write, so no thread reads a value already doubled.
+                constexpr int kPer = (kExt + kSearchThreads - 1) / kSearchThreads;
+                float nv[kPer];
+#pragma unroll
+                for (int k = 0; k < kPer; ++k) {
+                    const int i = tid + k * kSearchThreads;
+                    nv[k] = i + 2 * w <= kExt ? box[i] + box[i + w] : 0.f;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < kPer; ++k) {
+                    const int i = tid + k * kSearchThreads;
+                    if (i < kExt)
+                        box[i] = nv[k];
+                }
+                __syncthreads();
+            }
+        }
+    } else {
+        best = Cand{0.f, 0, 1};
+    }
+    cred[tid] = best;
+    __syncthreads();
+    for (int o = kSearchThreads / 2; o > 0; o >>= 1) {
+        if (tid < o && better(cred[tid + o], cred[tid]))
+            cred[tid] = cred[tid + o];
+        __syncthreads();
+    }
+    if (tid == 0) {
+        snr_out[blockIdx.x] = cred[0].snr;
+        t_out[blockIdx.x] = cred[0].t;
+        w_out[blockIdx.x] = cred[0].w;
+    }
+}
+
+}  // namespace
+}  // namespace dd
+
+using namespace dd;
+
+extern "C" int dd_search_boxcar(const float *d_rows, int64_t row_stride, int32_t n_rows, int64_t n_samples,
+                                int32_t n_widths, float *d_snr, int32_t *d_t, int32_t *d_width, void *stream) {
+    clear_error();
+    if (!d_rows || !d_snr || !d_t || !d_width)
+        return fail(DD_EINVAL, "NULL argument");
+    if (n_rows < 1 || n_samples < 1 || n_samples > 0x7fffffffLL)
+        return fail(DD_EINVAL, "need n_rows >= 1 and 1 <= n_samples < 2^31");
+    if (n_widths < 1 || n_widths > kMaxWidthsLog)
+        return fail(DD_EINVAL, "n_widths must be in [1, %d] (got %d)", kMaxWidthsLog, n_widths);
+    if (row_stride < n_samples)
+        return fail(DD_ESHAPE, "row_stride %lld < n_samples %lld", (long long)row_stride, (long long)n_samples);
+    if (reinterpret_cast<uintptr_t>(d_rows) % 4 || reinterpret_cast<uintptr_t>(d_snr) % 4 ||
+        reinterpret_cast<uintptr_t>(d_t) % 4 || reinterpret_cast<uintptr_t>(d_width) % 4)
+        return fail(DD_ESHAPE, "pointers must be 4-byte aligned");
+    hipLaunchKernelGGL(boxcar_search_kernel, dim3(static_cast<uint32_t>(n_rows)), dim3(kSearchThreads), 0,
+                       static_cast<hipStream_t>(stream), d_rows, row_stride, n_samples, n_widths, d_snr, d_t,
+                       d_width);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(DD_EHIP, "search launch failed: %s", hipGetErrorString(e));
+    return DD_OK;
+}

@@ -160,6 +160,25 @@ def test_realtime_rejects_bad_arguments_before_gpu_work():
     assert L.dd_realtime_destroy(None) == _lib.DD_OK
 
 
+def test_search_rejects_bad_arguments_before_gpu_work():
+    L = _lib.lib()
+    R, O = _fake(0x100000), _fake(0x200000)
+    ok = (R, 100, 4, 100, 8, O, O, O, None)
+    def call(i, v):
+        a = list(ok)
+        a[i] = v
+        return L.dd_search_boxcar(*a)
+    assert call(0, None) == _lib.DD_EINVAL
+    assert call(5, None) == _lib.DD_EINVAL
+    assert call(2, 0) == _lib.DD_EINVAL          # no rows
+    assert call(3, 0) == _lib.DD_EINVAL          # no samples
+    assert call(4, 0) == _lib.DD_EINVAL          # widths
+    assert call(4, 13) == _lib.DD_EINVAL
+    assert call(1, 99) == _lib.DD_ESHAPE         # stride < samples
+    assert call(0, _fake(0x100002)) == _lib.DD_ESHAPE
+    assert L.dd_last_error()
+
+
 def test_tile_variants_cover_paper_parameters():
     """Sec. III-B: work-items and elements per work-item, in time and in DM."""
     vs = tile_variants()
