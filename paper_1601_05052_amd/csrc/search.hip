@@ -10,7 +10,7 @@
 // (0 at (0, 1) when sigma is 0).
 //
 // One work-group per row.  Mean and standard deviation are accumulated in
-// binary64 (two passes over the row); the centred samples are formed in
+// binary64 (one pass over the row); the centred samples are formed in
 // binary64 and rounded to binary32, so the row's offset never enters the
 // binary32 boxcar sums.  Boxcars are built by doubling in LDS,
 // B_2w(t) = B_w(t) + B_w(t + w), over chunks of the row with a halo of the
@@ -73,16 +73,34 @@ __global__ __launch_bounds__(kSearchThreads) void boxcar_search_kernel(const flo
     const int tid = threadIdx.x;
     const float *y = rows + static_cast<int64_t>(blockIdx.x) * row_stride;
 
-    double s = 0.0;
-    for (int64_t i = tid; i < S; i += kSearchThreads)
-        s += static_cast<double>(y[i]);
-    const double mu = block_sum(s, red) / static_cast<double>(S);
-    double q = 0.0;
-    for (int64_t i = tid; i < S; i += kSearchThreads) {
-        const double c = static_cast<double>(y[i]) - mu;
-        q += c * c;
+    // One pass: sums of d = y - y[0] and d^2 in binary64 (the shift keeps the
+    // terms near the row's spread), 16-byte loads when the row allows.
+    const double k0 = static_cast<double>(y[0]);
+    double s = 0.0, q = 0.0;
+    auto acc = [&](float v) {
+        const double d = static_cast<double>(v) - k0;
+        s += d;
+        q += d * d;
+    };
+    int64_t done = 0;
+    if ((reinterpret_cast<uintptr_t>(y) & 15) == 0) {
+        const float4 *y4 = reinterpret_cast<const float4 *>(y);
+        const int64_t n4 = S / 4;
+        for (int64_t i = tid; i < n4; i += kSearchThreads) {
+            const float4 v = y4[i];
+            acc(v.x);
+            acc(v.y);
+            acc(v.z);
+            acc(v.w);
+        }
+        done = 4 * n4;
     }
-    const double sigma = sqrt(block_sum(q, red) / static_cast<double>(S));
+    for (int64_t i = done + tid; i < S; i += kSearchThreads)
+        acc(y[i]);
+    const double sd = block_sum(s, red) / static_cast<double>(S);
+    const double qd = block_sum(q, red) / static_cast<double>(S);
+    const double mu = k0 + sd;
+    const double sigma = sqrt(fmax(qd - sd * sd, 0.0));
 
     Cand best{-INFINITY, 0, 1};
     if (sigma > 0.0) {
@@ -92,33 +110,59 @@ __global__ __launch_bounds__(kSearchThreads) void boxcar_search_kernel(const flo
             wmax *= 2;
         for (int64_t c0 = 0; c0 < S; c0 += kChunk) {
             __syncthreads();  // the previous chunk's boxcars are consumed
-            for (int i = tid; i < kExt; i += kSearchThreads) {
-                const int64_t g = c0 + i;
-                box[i] = g < S ? static_cast<float>(static_cast<double>(y[g]) - mu) : 0.f;
+            if ((reinterpret_cast<uintptr_t>(y) & 15) == 0) {  // c0 is a multiple of 4
+                for (int i = 4 * tid; i < kExt; i += 4 * kSearchThreads) {
+                    const int64_t g = c0 + i;
+                    float v[4];
+                    if (g + 3 < S) {
+                        const float4 u = *reinterpret_cast<const float4 *>(y + g);
+                        v[0] = u.x;
+                        v[1] = u.y;
+                        v[2] = u.z;
+                        v[3] = u.w;
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 4; ++k)
+                            v[k] = g + k < S ? y[g + k] : 0.f;
+                    }
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        box[i + k] = g + k < S ? static_cast<float>(static_cast<double>(v[k]) - mu) : 0.f;
+                }
+            } else {
+                for (int i = tid; i < kExt; i += kSearchThreads) {
+                    const int64_t g = c0 + i;
+                    box[i] = g < S ? static_cast<float>(static_cast<double>(y[g]) - mu) : 0.f;
+                }
             }
             __syncthreads();
             // box holds B_w(c0 + i) for i + w <= kExt; widths double per level.
+            // Each level scores the boxcars starting in this chunk and, in the
+            // same pass, forms B_2w(i) = B_w(i) + B_w(i + w) for i + 2w <= kExt:
+            // all reads, then a barrier, then the writes, so no thread reads a
+            // value already doubled.
+            constexpr int kPer = (kExt + kSearchThreads - 1) / kSearchThreads;
+            static_assert(kChunk % kSearchThreads == 0, "chunk starts split evenly over the threads");
             for (int32_t w = 1;; w *= 2) {
                 const float scale = inv_sigma * rsqrtf(static_cast<float>(w));
-                for (int i = tid; i < kChunk; i += kSearchThreads) {
-                    const int64_t t = c0 + i;
-                    if (t + w <= S) {
-                        const Cand c{box[i] * scale, static_cast<int32_t>(t), w};
-                        if (better(c, best))
-                            best = c;
-                    }
-                }
-                if (w >= wmax)
-                    break;
-                // B_2w(i) = B_w(i) + B_w(i + w) for i + 2w <= kExt: read all,
-                // then write, so no thread reads a value already doubled.
-                constexpr int kPer = (kExt + kSearchThreads - 1) / kSearchThreads;
+                const bool last = w >= wmax;
                 float nv[kPer];
 #pragma unroll
                 for (int k = 0; k < kPer; ++k) {
                     const int i = tid + k * kSearchThreads;
-                    nv[k] = i + 2 * w <= kExt ? box[i] + box[i + w] : 0.f;
+                    const float b = i < kExt ? box[i] : 0.f;
+                    if (k < kChunk / kSearchThreads) {
+                        const int64_t t = c0 + i;
+                        if (t + w <= S) {
+                            const Cand c{b * scale, static_cast<int32_t>(t), w};
+                            if (better(c, best))
+                                best = c;
+                        }
+                    }
+                    nv[k] = !last && i + 2 * w <= kExt ? b + box[i + w] : 0.f;
                 }
+                if (last)
+                    break;
                 __syncthreads();
 #pragma unroll
                 for (int k = 0; k < kPer; ++k) {
