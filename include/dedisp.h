@@ -124,7 +124,9 @@ int dd_dedisperse(const dd_plan *plan, const void *d_in, dd_dtype in_type, int64
  *   d_grad_in[ch*in_stride + tau] = sum over i with 0 <= tau - delay[i][ch] < n_samples
  *                                   of d_grad_out[i*out_stride + tau - delay[i][ch]]
  * for ch < n_channels and tau < n_samples + max_delay.  Written as a gather
- * per channel over DMs (no atomics), so results are deterministic.
+ * per channel over DMs (no atomics), so results are deterministic.  The
+ * direct tile variants with row blocks (dd_tile_info kind 2) enqueue one
+ * kernel per block of DMs, d_grad_in holding the partial sums in between.
  *   d_grad_out  device float, n_dm rows of out_stride >= n_samples
  *   d_grad_in   device float, n_channels rows of in_stride >= n_samples + max_delay;
  *               columns [0, n_samples + max_delay) are overwritten (zeros where

@@ -61,15 +61,22 @@ __global__ void __launch_bounds__(64 * NW)
                                                     lds_p);
 }
 
-template <typename TIn, int IT, int NW, int U, bool CARRY>
+// VEC: consecutive ownership with 16-byte loads (float32 input only; other
+// input types take the strided form).
+template <typename TIn, int IT, int NW, int U, bool CARRY, bool VEC>
 __global__ void __launch_bounds__(64 * NW)
     srs_direct_kernel(const TIn *__restrict__ in, float *__restrict__ out, const int32_t *__restrict__ rel,
                       const int32_t *__restrict__ base, const int32_t *__restrict__ span, SrsDims d, int32_t r_begin,
                       int32_t r_end) {
     int32_t tile_t, tile_a;
     dev::tile_of_block(d, tile_t, tile_a);
-    dev::srs_tile_direct<TIn, IT, NW, U, CARRY>(in, out, dev::as_ctab(rel), dev::as_ctab(base), dev::as_ctab(span), d,
-                                                tile_t, tile_a, r_begin, r_end);
+    if constexpr (VEC && sizeof(TIn) == 4)
+        dev::srs_tile_direct_vec<IT, NW, U, CARRY>(reinterpret_cast<const float *>(in), out, dev::as_ctab(rel),
+                                                   dev::as_ctab(base), dev::as_ctab(span), d, tile_t, tile_a, r_begin,
+                                                   r_end);
+    else
+        dev::srs_tile_direct<TIn, IT, NW, U, CARRY>(in, out, dev::as_ctab(rel), dev::as_ctab(base), dev::as_ctab(span),
+                                                    d, tile_t, tile_a, r_begin, r_end);
 }
 
 // Multi-beam forms: work-group g takes items[g] = (beam << 24) | logical tile
@@ -209,12 +216,12 @@ hipError_t launch_ldsp(const SrsArgs &a, const SrsDims &d, uint32_t blocks, size
 // RB > 0: the rows are summed in blocks of RB by successive launches, each
 // continuing the partial sums the previous one left in the output (the
 // kernel boundary keeps every work-group within one block of rows).
-template <typename TIn, int IT, int NW, int U, int RB>
+template <typename TIn, int IT, int NW, int U, int RB, bool VEC>
 hipError_t launch_direct(const SrsArgs &a, const SrsDims &d, uint32_t blocks, size_t, hipStream_t s) {
     const int32_t step = RB > 0 ? RB : d.n_rows;
     for (int32_t r0 = 0; r0 < d.n_rows; r0 += step) {
         const int32_t r1 = d.n_rows - r0 > step ? r0 + step : d.n_rows;
-        hipLaunchKernelGGL((srs_direct_kernel<TIn, IT, NW, U, (RB > 0)>), dim3(blocks), dim3(64 * NW), 0, s,
+        hipLaunchKernelGGL((srs_direct_kernel<TIn, IT, NW, U, (RB > 0), VEC>), dim3(blocks), dim3(64 * NW), 0, s,
                            static_cast<const TIn *>(a.in), a.out, a.rel, a.base, a.span, d, r0, r1);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)

@@ -575,5 +575,106 @@ __device__ __forceinline__ void srs_tile_direct(const TIn *__restrict__ in, floa
     }
 }
 
+// Direct form with consecutive ownership, float32 input: lane l owns samples
+// t0 + 4l + 256q + i (q < IT/4, i < 4) and reads each row's operands with
+// 16-byte buffer loads (one per q), a quarter of the load instructions of
+// srs_tile_direct.  Rows whose window starts before sample 0 fall back to
+// per-sample loads.  Same rows, same order, same partial-sum carry and tile
+// rotation as srs_tile_direct, so the sums are bit-identical to it.
+template <int IT, int NW, int U, bool CARRY>
+__device__ __forceinline__ void srs_tile_direct_vec(const float *__restrict__ in, float *__restrict__ out,
+                                                    ctab *__restrict__ rel, ctab *__restrict__ base, ctab *span,
+                                                    const SrsDims &d, int32_t tile_t, int32_t tile_a,
+                                                    int32_t r_begin, int32_t r_end) {
+    static_assert(IT % 4 == 0, "16-byte pieces");
+    constexpr int TT = 64 * IT;
+    constexpr int Q = IT / 4;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    ctab *base_tile = base + static_cast<int64_t>(tile_a) * d.n_rows;
+    ctab *rel_tile = rel + static_cast<int64_t>(tile_a) * d.n_rows * NW + wave;
+    if constexpr (CARRY) {
+        const int32_t mid = __builtin_amdgcn_readfirstlane(base_tile[r_begin + (r_end - r_begin) / 2]);
+        const int32_t shift = (mid >= 0 ? mid / TT : -((-mid + TT - 1) / TT)) % d.n_t_tiles;  // (-n, n)
+        tile_t -= shift;
+        if (tile_t < 0)
+            tile_t += d.n_t_tiles;
+        else if (tile_t >= d.n_t_tiles)
+            tile_t -= d.n_t_tiles;
+    }
+    const int64_t t0 = static_cast<int64_t>(tile_t) * TT;
+    const int32_t n_bytes = static_cast<int32_t>(d.in_valid * 4);
+    const int32_t ag = tile_a * NW + wave;
+    float *dst = out + static_cast<int64_t>(min(ag, d.n_acc - 1)) * d.out_stride;
+    // Output row as a buffer clipped to [0, n_t): out-of-range dwords read 0.
+    const __amdgpu_buffer_rsrc_t out_rs =
+        __builtin_amdgcn_make_buffer_rsrc(dst, 0, static_cast<int32_t>(d.n_t * 4), kBufferFlags);
+    const uint32_t lane_off = static_cast<uint32_t>(t0 + 4 * lane) * 4u;  // < 2^31: t0 < n_t < 2^29
+    v4f acc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        if (CARRY && r_begin > 0 && ag < d.n_acc)
+            acc[q] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(out_rs, lane_off + q * 1024u, 0, 0));
+        else
+            acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+    int32_t r_from = r_begin, r_to = r_end;
+    if (span) {
+        const int64_t k = 2 * (static_cast<int64_t>(tile_a) * d.n_t_tiles + tile_t);
+        r_from = max(r_from, __builtin_amdgcn_readfirstlane(span[k]));
+        r_to = min(r_to, __builtin_amdgcn_readfirstlane(span[k + 1]));
+    }
+    for (int32_t r0 = r_from; r0 < r_to; r0 += U) {
+        v4f v[U][Q];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t r = min(r0 + u, r_to - 1);
+            const int64_t g0 = t0 + __builtin_amdgcn_readfirstlane(base_tile[r]) +
+                               __builtin_amdgcn_readfirstlane(rel_tile[static_cast<int64_t>(r) * NW]);
+            const float *rp = in + static_cast<int64_t>(r) * d.in_stride;
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(rp), 0, n_bytes, kBufferFlags);
+            if (r0 + u >= r_to) {
+#pragma unroll
+                for (int q = 0; q < Q; ++q)
+                    v[u][q] = v4f{0.f, 0.f, 0.f, 0.f};
+            } else if (g0 >= 0) {  // wave-uniform
+                const uint32_t voff = static_cast<uint32_t>(g0 + 4 * lane) * 4u;
+#pragma unroll
+                for (int q = 0; q < Q; ++q)
+                    v[u][q] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(rs, voff + q * 1024u, 0, 0));
+            } else {
+#pragma unroll
+                for (int q = 0; q < Q; ++q)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int64_t g = g0 + 4 * lane + 256 * q + i;
+                        v[u][q][i] = buffer_ld<float>(rs, g >= 0 ? static_cast<uint32_t>(g) * 4u : kOutOfRange);
+                    }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                acc[q] += v[u][q];
+    }
+    if (ag < d.n_acc) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int64_t t = t0 + 4 * lane + 256 * q;
+            if (t + 3 < d.n_t) {
+                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4i, acc[q]), out_rs, lane_off + q * 1024u, 0,
+                                                       0);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (t + i < d.n_t)
+                        dst[t + i] = acc[q][i];
+            }
+        }
+    }
+}
+
 }  // namespace dev
 }  // namespace dd

@@ -15,7 +15,7 @@ namespace {
 
 #define X_LDS(ID, IT, TDW, NW, RATE) {ID, IT, TDW, NW, KIND_LDS, 0, 0, 0, RATE},
 #define X_LDSP(ID, IT, TDW, NW, RPW, KMAX, RATE) {ID, IT, TDW, NW, KIND_LDS, RPW, 0, KMAX, RATE},
-#define X_DIRECT(ID, IT, NW, U, RB, RATE) {ID, IT, 1, NW, KIND_DIRECT, U, 0, 0, RATE},
+#define X_DIRECT(ID, IT, NW, U, RB, V, RATE) {ID, IT, 1, NW, KIND_DIRECT, U, 0, 0, RATE},
 #define X_RW(ID, IT, TDW, NWR, NW, RPW, KMAX, RATE) {ID, IT, TDW, NW, KIND_REGWIN, RPW, NWR, KMAX, RATE},
 #define X_RWO(ID, IT, TDW, NWR, NW, RPW, KMAX, OCC, RATE) {ID, IT, TDW, NW, KIND_REGWIN, RPW, NWR, KMAX, RATE},
 const Variant kVariants[] = {DD_VARIANT_LIST};
