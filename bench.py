@@ -141,6 +141,20 @@ def measure_forward(torch, dd, setup, dtype, steps, warmup, stream, numpy_input=
                 compulsory_bytes=compulsory_bytes(setup, bpe, plan), tile=plan.get_tile(dtype=code)), plan
 
 
+def measure_adjoint(torch, dd, setup, steps, warmup, stream):
+    """Tuned adjoint of one beam: gradient rows [D][S] -> [C][T_in]."""
+    plan = dd.Plan.from_setup(setup)
+    plan.autotune(dd.DD_ADJOINT, dd.DD_F32, reps=3)
+    plan.prepare(dd.DD_ADJOINT, dd.DD_F32)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(setup.seed)
+    gy = torch.randn((setup.n_dm, setup.n_samples), generator=g, device="cuda")
+    gx = torch.empty((setup.n_channels, plan.input_samples), device="cuda")
+    ms, wall = timed(torch, lambda: dd.dedisperse_adjoint(gy, plan, out=gx), steps, warmup, stream)
+    return dict(ms=ms, wall_s=wall, gflops=setup.adds / (ms * 1e-3) / 1e9,
+                compulsory_bytes=compulsory_bytes(setup, 4, plan), tile=plan.get_tile(direction=dd.DD_ADJOINT))
+
+
 def cpu_baseline(setup, budget_s=12.0):
     """The FP64 oracle on a bounded sample of the workload: the full input,
     the first n trial DMs, n chosen so the timed run takes ~budget_s."""
@@ -208,16 +222,9 @@ def extras(torch, dd, stream, steps):
     r["hbm_GBps"] = r["compulsory_bytes"] / (r["ms"] * 1e-3) / 1e9
     res["lofar_f32"] = r
     log("lofar f32: %.3f ms %.1f GFLOP/s" % (r["ms"], r["gflops"]))
-    lp = dd.Plan.from_setup(synth.LOFAR)
-    lp.autotune(dd.DD_ADJOINT, dd.DD_F32, reps=3)
-    lp.prepare(dd.DD_ADJOINT, dd.DD_F32)
-    gy = torch.randn((synth.LOFAR.n_dm, synth.LOFAR.n_samples), device="cuda")
-    gx = torch.empty((synth.LOFAR.n_channels, lp.input_samples), device="cuda")
-    ms_la, _ = timed(torch, lambda: dd.dedisperse_adjoint(gy, lp, out=gx), steps, 2, stream)
-    res["lofar_adjoint"] = dict(ms=ms_la, gflops=synth.LOFAR.adds / (ms_la * 1e-3) / 1e9,
-                                tile=lp.get_tile(direction=dd.DD_ADJOINT))
-    log("lofar adjoint: %.3f ms (variant %d)" % (ms_la, res["lofar_adjoint"]["tile"]))
-    del gy, gx
+    r = measure_adjoint(torch, dd, synth.LOFAR, steps, 2, stream)
+    res["lofar_adjoint"] = dict(ms=r["ms"], gflops=r["gflops"], tile=r["tile"])
+    log("lofar adjoint: %.3f ms (variant %d)" % (r["ms"], r["tile"]))
     # low precision storage, Apertif
     for dt in ("u8", "f16"):
         r, _ = measure_forward(torch, dd, synth.APERTIF, dt, steps, 2, stream)
@@ -349,6 +356,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="apertif", choices=["apertif", "lofar"])
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="time the adjoint of the workload in the headline slot (for its profile)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune-study", metavar="JSON",
                     help="run the auto-tuning study over 2..4096 DMs for both setups, write it here, exit")
@@ -380,14 +389,18 @@ def main():
     x = synth.make_input(setup, plan0.input_samples, "f32", arrivals=arrivals)
     log("workload %s: C=%d D=%d S=%d T_in=%d" % (setup.name, setup.n_channels, setup.n_dm, setup.n_samples,
                                                   plan0.input_samples))
-    r, plan = measure_forward(torch, dd, setup, "f32", args.steps, args.warmup, stream, numpy_input=x)
+    if args.adjoint:
+        r = measure_adjoint(torch, dd, setup, args.steps, args.warmup, stream)
+    else:
+        r, plan = measure_forward(torch, dd, setup, "f32", args.steps, args.warmup, stream, numpy_input=x)
     ms = r["ms"]
-    log("forward f32: %.4f ms/step, %.1f GFLOP/s, tile %d" % (ms, r["gflops"], r["tile"]))
+    log("%s f32: %.4f ms/step, %.1f GFLOP/s, tile %d" % ("adjoint" if args.adjoint else "forward", ms, r["gflops"],
+                                                          r["tile"]))
     achieved_tflops = setup.adds / (ms * 1e-3) / 1e12
     hbm_gbps = r["compulsory_bytes"] / (ms * 1e-3) / 1e9
     line = {
-        "metric": "dedispersion GFLOP/s (one FLOP per channel addition), %s-shaped beam, FP32"
-                  % {"apertif": "Apertif", "lofar": "LOFAR"}[args.workload],
+        "metric": "dedispersion%s GFLOP/s (one FLOP per channel addition), %s-shaped beam, FP32"
+                  % (" adjoint" if args.adjoint else "", {"apertif": "Apertif", "lofar": "LOFAR"}[args.workload]),
         "value": round(r["gflops"], 2),
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -408,7 +421,7 @@ def main():
                    "tile_variant": r["tile"]},
         "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": round(ADD_PEAK_TFLOPS, 1),
                      "unit": "TFLOP/s", "frac": round(achieved_tflops / ADD_PEAK_TFLOPS, 4),
-                     "traffic": measured_traffic(setup.name, r["tile"])},
+                     "traffic": None if args.adjoint else measured_traffic(setup.name, r["tile"])},
         "hbm": {"compulsory_bytes": r["compulsory_bytes"], "achieved_GBps": round(hbm_gbps, 1),
                 "peak_GBps": HBM_PEAK_GBPS, "frac": round(hbm_gbps / HBM_PEAK_GBPS, 4)},
         "paper_context": {"hd7970_2000dms_s": 0.106, "hd7970_GFLOPs": round(2000 * 1024 * 20000 / 0.106 / 1e9, 1),
