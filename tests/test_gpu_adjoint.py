@@ -94,6 +94,32 @@ def test_adjoint_whole_channel_rows(s):
         gates.exact(gx[ch], ref, what="adjoint ch %d" % ch)
 
 
+@pytest.mark.parametrize("s", [synth.APERTIF, synth.LOFAR], ids=lambda s: s.name)
+def test_adjoint_full_size_every_fitting_variant(s):
+    """The benchmark tunes the adjoint and times whichever variant wins, so
+    every variant that fits the full-size adjoint is checked, bit for bit on
+    integer values, on three whole channel rows."""
+    plan = Plan.from_setup(s)
+    table = oracle_delays(s)
+    T = plan.input_samples
+    gy = synth.integers_f32(s.n_dm, s.n_samples, seed=43, lo=-3, hi=3)
+    chans = (0, s.n_channels // 2, s.n_channels - 1)
+    refs = {ch: oracle.adjoint(gy, np.ascontiguousarray(table[:, ch:ch + 1]), T)[0] for ch in chans}
+    gyd = to_dev(gy)
+    checked = 0
+    for vid, *_ in tile_variants():
+        try:
+            plan.set_tile(vid, direction=DD_ADJOINT)
+        except Exception:
+            continue
+        gx = dedisperse_adjoint(gyd, plan)
+        for ch in chans:
+            gates.exact(to_host(gx[ch]), refs[ch], what="%s adjoint variant %d ch %d" % (s.name, vid, ch))
+        checked += 1
+    plan.set_tile(-1, direction=DD_ADJOINT)
+    assert checked >= 5
+
+
 def _loss_grad_reference(x, w, table, S):
     """Gradient of sum w * (A x)^2 is 2 A^T (w * A x), all in FP64."""
     y = oracle.dedisperse(x, table, S)
