@@ -57,6 +57,27 @@ __global__ __launch_bounds__(256) void copy_rows(T *__restrict__ dst, const T *_
         d[i] = s[i];
 }
 
+// Byte rows whose source and destination have the same address modulo 4:
+// up to three head bytes, whole 4-byte words, up to three tail bytes.
+__global__ __launch_bounds__(256) void copy_rows_words(char *__restrict__ dst, const char *__restrict__ src,
+                                                       int64_t pitch_bytes, int64_t n_bytes) {
+    const int64_t ch = blockIdx.y;
+    char *d = dst + ch * pitch_bytes;
+    const char *s = src + ch * pitch_bytes;
+    const int64_t head = min<int64_t>((4 - (reinterpret_cast<uintptr_t>(d) & 3)) & 3, n_bytes);
+    const int64_t words = (n_bytes - head) / 4;
+    const int64_t tail = head + 4 * words;
+    const int64_t tid = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (tid < head)
+        d[tid] = s[tid];
+    uint32_t *dw = reinterpret_cast<uint32_t *>(d + head);
+    const uint32_t *sw = reinterpret_cast<const uint32_t *>(s + head);
+    for (int64_t w = tid; w < words; w += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        dw[w] = sw[w];
+    if (tid < n_bytes - tail)
+        d[tail + tid] = s[tail + tid];
+}
+
 size_t elem_size(int32_t t) { return t == DD_F32 ? 4 : t == DD_F16 ? 2 : 1; }
 
 void rt_free(dd_realtime *r) {
@@ -94,6 +115,16 @@ hipError_t launch_tail(const dd_realtime *r, int s) {
     const size_t src_off = static_cast<size_t>(r->lead + p->S) * r->es;
     char *dst = static_cast<char *>(r->win[s]) + off;
     const char *src = static_cast<const char *>(r->win[1 - s]) + src_off;
+    if (r->es != 4 && (static_cast<int64_t>(p->S) * static_cast<int64_t>(r->es)) % 4 == 0) {
+        // Window bases and rows are 64-byte aligned, so source and destination
+        // differ by S * es bytes modulo 4: here a multiple of 4.
+        const int64_t n_bytes = n * static_cast<int64_t>(r->es);
+        const dim3 grid_w(static_cast<uint32_t>(std::min<int64_t>((n_bytes / 4 + 255) / 256, 32)) + 1u,
+                          static_cast<uint32_t>(p->C));
+        hipLaunchKernelGGL(copy_rows_words, grid_w, dim3(256), 0, r->copy, dst, src,
+                           static_cast<int64_t>(r->pitch * r->es), n_bytes);
+        return hipGetLastError();
+    }
     const dim3 grid(static_cast<uint32_t>(std::min<int64_t>((n + 255) / 256, 32)), static_cast<uint32_t>(p->C));
     if (r->es == 4)
         hipLaunchKernelGGL(copy_rows<uint32_t>, grid, dim3(256), 0, r->copy, reinterpret_cast<uint32_t *>(dst),

@@ -61,19 +61,29 @@ def test_tiny_stream_against_oracle(dtype):
     rt.close()
 
 
-def test_chunks_shorter_than_max_delay_integer_exact():
-    """S < max_delay: a window spans several earlier chunks."""
+@pytest.mark.parametrize("dtype,S", [("f32", 100), ("u8", 100), ("u8", 101), ("f16", 102), ("f16", 103)])
+def test_chunks_shorter_than_max_delay_exact(dtype, S):
+    """S < max_delay: a window spans several earlier chunks.  Chunk lengths
+    whose byte size is and is not a multiple of 4 (the window tail is then
+    moved by words or by samples).  Integer-valued samples: exact."""
     torch = torch_mod()
-    args = (64, 1400.0, 1.5625, 5e-5, 0.0, 0.5, 128, 100)
+    args = (64, 1400.0, 1.5625, 5e-5, 0.0, 0.5, 128, S)
     plan = Plan(*args)
     table = oracle.delay_table(*args[:7])
-    S, M, K = 100, plan.max_delay, 9
+    M, K = plan.max_delay, 9
     assert M > 3 * S
-    x = synth.integers_f32(64, K * S, seed=21)
-    rt = Realtime(plan, torch.float32)
+    if dtype == "u8":
+        x = synth.noise_u8(64, K * S, seed=21)
+    else:
+        x = synth.integers_f32(64, K * S, seed=21)
+        if dtype == "f16":
+            x = x.astype(np.float16)
+    tdt = {"f32": torch.float32, "u8": torch.uint8, "f16": torch.float16}[dtype]
+    rt = Realtime(plan, tdt)
     for k in range(K):
         y = to_host(rt.push(host_chunk(torch, x[:, k * S:(k + 1) * S], pinned=True)))
-        gates.exact(y, oracle.dedisperse(stream_windows(x, M, S, k), table, S), what="push %d" % k)
+        w = stream_windows(x, M, S, k).astype(np.float64)
+        gates.exact(y, oracle.dedisperse(w, table, S), what="%s push %d" % (dtype, k))
     rt.close()
 
 
