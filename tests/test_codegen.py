@@ -53,3 +53,18 @@ def test_index_mode_regions_balanced():
     text = _listing()
     for blk in re.findall(r";;#ASMSTART\n(.*?);;#ASMEND", text, re.S):
         assert blk.count("s_set_gpr_idx_on") == blk.count("s_set_gpr_idx_off"), blk[:120]
+
+
+def test_no_packed_fp32_instructions():
+    """Every kernel unit is built without packed FP32 arithmetic (v_pk_add_f32,
+    v_pk_mul_f32, v_pk_fma_f32): ordinary float code only."""
+    text = _listing()
+    found = sorted(set(re.findall(r"\bv_pk_(?:add|mul|fma)_f32\b", text)))
+    assert not found, found
+
+
+def test_direct_kernels_have_no_scratch():
+    ks = [k for k in _kernels(_listing()) if "direct" in k[0]]
+    assert ks
+    for name, _, scratch in ks:
+        assert scratch == 0, name
