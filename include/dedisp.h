@@ -169,8 +169,8 @@ int dd_autotune(dd_plan *plan, dd_direction direction, dd_dtype in_type, int32_t
 
 /* ---------------------------------------------------------------- batches */
 
-/* Many independent beams (Sec. III-A treats one beam without loss of
- * generality; beams are independent) dedispersed by ONE HIP graph launch.
+/* Many independent beams (Sec. III-A describes one beam; the method applies
+ * unchanged to each of many) dedispersed by ONE HIP graph launch.
  * Each beam uses the forward tile variant its plan would use alone (forced
  * by dd_plan_set_tile, tuned by dd_autotune / dd_batch_autotune, else the
  * cost model's choice); beams sharing a variant are served by one launch of

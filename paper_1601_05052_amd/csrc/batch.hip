@@ -1,6 +1,6 @@
-// Batched dedispersion: many independent beams (the method is stated for one
-// beam without loss of generality, and beams share nothing, Sec. II / III-A)
-// run from ONE HIP graph launch.
+// Batched dedispersion: many independent beams (the method is described for
+// one beam and applies unchanged to each of many; beams share nothing,
+// Sec. II / III-A) run from ONE HIP graph launch.
 //
 // Every beam keeps the tile variant its plan would use on its own (forced,
 // tuned by dd_autotune / dd_batch_autotune, or the cost model's choice).

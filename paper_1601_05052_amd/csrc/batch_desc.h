@@ -1,7 +1,7 @@
 // Descriptors shared by the batched (multi-beam) kernels and their host side.
 //
-// A batch runs many independent beams (the method treats one beam without
-// loss of generality; beams share nothing, Sec. II / III-A).  Beams that use
+// A batch runs many independent beams (the method is described for one beam
+// and applies unchanged to each; beams share nothing, Sec. II / III-A).  Beams that use
 // the same tile variant are served by one launch of that variant's multi-beam
 // kernel: work-group g reads items[g] = (beam << 24) | tile and runs the same
 // tile routine as the single-beam kernel on that beam's tables and pointers.
