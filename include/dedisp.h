@@ -227,8 +227,9 @@ int dd_batch_destroy(dd_batch *batch);
  *
  * dd_realtime_create binds the plan (which must outlive the object), the
  * input type and the compute stream; it allocates two device windows of
- * n_channels x T_in samples and two staging buffers of n_channels x S, creates
- * its own non-blocking copy stream, and builds the plan's forward tables.
+ * n_channels x T_in samples (host chunks are copied straight into them),
+ * creates its own non-blocking copy stream, and builds the plan's forward
+ * tables.
  *   DD_EINVAL  NULL argument, unknown dtype
  *   DD_ENOMEM / DD_EHIP  allocation or stream set-up failed */
 typedef struct dd_realtime dd_realtime;
@@ -253,8 +254,8 @@ int dd_realtime_push(dd_realtime *rt, const void *h_chunk, int64_t h_stride, flo
 /* Number of chunks pushed so far (the next push is chunk *n_pushed). */
 int dd_realtime_pushed(const dd_realtime *rt, int64_t *n_pushed);
 
-/* Waits for the object's outstanding copies and kernels (and the bound
- * stream, if anything was pushed), then frees it.  NULL is accepted. */
+/* Waits for the object's outstanding copies and for the last kernels that
+ * read its windows, then frees it.  NULL is accepted. */
 int dd_realtime_destroy(dd_realtime *rt);
 
 /* ---------------------------------------------------------------- candidate search */
