@@ -371,8 +371,8 @@ def main():
                     help="also run a plain 256 MiB device copy (scale for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: dedispersion beams are independent and this build runs on a "
-              "single MI355X; --gpus %d is not supported" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU: beams are independent, so several GPUs would each run their own "
+              "beams with no exchange; multi-GPU runs are not implemented (--gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -62,7 +62,7 @@ typedef enum dd_status {
     DD_ESHAPE = -2,       /* stride / size / alignment inconsistent with the plan */
     DD_ENOMEM = -3,       /* host or device allocation failed */
     DD_EHIP = -4,         /* a HIP runtime call or kernel launch failed */
-    DD_EUNSUPPORTED = -5  /* valid request this build cannot serve */
+    DD_EUNSUPPORTED = -5  /* valid request the compiled tile variants cannot serve */
 } dd_status;
 
 /* ---------------------------------------------------------------- plans */
