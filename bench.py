@@ -365,6 +365,8 @@ def main():
     ap.add_argument("--adjoint", action="store_true",
                     help="time the adjoint of the workload in the headline slot (for its profile)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--realtime", action="store_true",
+                    help="only the streaming measurement (Apertif u8 chunks from pinned host memory), one JSON line")
     ap.add_argument("--tune-study", metavar="JSON",
                     help="run the auto-tuning study over 2..4096 DMs for both setups, write it here, exit")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -381,6 +383,9 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     setup = synth.WORKLOADS[args.workload]
+    if args.realtime:
+        print(json.dumps(realtime(torch, dd, stream, args.steps)), flush=True)
+        return
     if args.tune_study:
         study = tune_study(torch, dd, stream)
         with open(args.tune_study, "w") as f:
