@@ -1,8 +1,12 @@
 // Auto-tuning of the tile shape (Sclocco et al., Sec. IV-A): run every tile
 // variant that can serve the plan, on the plan's own sizes, and keep the
 // fastest.  Results can be cached in a text file keyed by device, direction,
-// input type and plan shape ("no single optimal configuration" exists across
-// setups and instances, Sec. V-A, so the key includes the whole setup).
+// input type and plan shape (the best configuration differs between setups and
+// instances, Sec. V-A, so the key includes the whole setup).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -21,6 +25,27 @@ int run_direction(const dd_plan *p, int direction, int32_t in_type, const Varian
 using namespace dd;
 
 namespace {
+
+// Tuning input: samples of magnitude 0.5..1 with random signs (float32,
+// float16) or random bytes (u8) from a counter hash, so the variants are timed
+// on data that toggles the adders as real data does (all-zero input draws
+// less power, lets the clock run higher and flatters some variants more than
+// others).
+__global__ __launch_bounds__(256) void fill_tuning_input(void *buf, int64_t n, int32_t elem_size) {
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        uint32_t x = static_cast<uint32_t>(i) * 0x9E3779B1u ^ static_cast<uint32_t>(i >> 32) * 0x85EBCA77u;
+        x ^= x >> 15;
+        x *= 0x2C1B3C6Du;
+        x ^= x >> 12;
+        if (elem_size == 4)
+            static_cast<uint32_t *>(buf)[i] = (x & 0x807FFFFFu) | 0x3F000000u;
+        else if (elem_size == 2)
+            static_cast<uint16_t *>(buf)[i] = static_cast<uint16_t>((x & 0x83FFu) | 0x3800u);
+        else
+            static_cast<uint8_t *>(buf)[i] = static_cast<uint8_t>(x >> 24);
+    }
+}
 
 std::string cache_key(const dd_plan *p, int direction, int32_t in_type) {
     int dev = 0;
@@ -88,8 +113,10 @@ int tune_candidates(const dd_plan *p, int direction, int32_t in_type, int32_t re
     int32_t best = -1;
     float best_t = 0.f;
     do {
-        if (hipMemsetAsync(d_in, 0, (size_t)in_rows * in_cols * esz, stream) != hipSuccess ||
-            hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        const int64_t n_in = in_rows * in_cols;
+        hipLaunchKernelGGL(fill_tuning_input, dim3(static_cast<uint32_t>(std::min<int64_t>((n_in + 255) / 256, 8192))),
+                           dim3(256), 0, stream, d_in, n_in, static_cast<int32_t>(esz));
+        if (hipGetLastError() != hipSuccess || hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
             rc = fail(DD_EHIP, "tuning setup failed");
             break;
         }
