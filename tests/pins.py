@@ -66,6 +66,23 @@ def check_delay_table(orc, args, n_check=1500, seed=0):
     check_delay_invariants(table, dm_first)
 
 
+def check_alg1_delays(delays_fn, seed=0):
+    """The pure-Python delay law (``alg1.delays``) against exact rational
+    rounding of Eq. (1) on the small plans and the tiny and FD-slice
+    workloads, every entry."""
+    plans = DELAY_ARGS + [(64, 1400.0, 1.5625, 5e-5, 0.0, 0.5, 128),
+                          (16, 1420.0, 64 * 300.0 / 1024, 1.0 / 20000, 0.0, 0.25, 32)]
+    for args in plans:
+        C, f_min, df, t_samp, dm_first, dm_step, D = args
+        table = np.array(delays_fn(*args), dtype=np.int64)
+        assert table.shape == (D, C), (args, table.shape)
+        for i in range(D):
+            for ch in range(C):
+                ex = exact_delay_samples(C, f_min, df, t_samp, dm_first, dm_step, i, ch)
+                assert int(table[i, ch]) == round(ex), (args, i, ch, int(table[i, ch]), float(ex))
+        check_delay_invariants(table, dm_first)
+
+
 def check_delay_invariants(table, dm_first):
     assert np.all(table[:, -1] == 0), "top channel must have zero delay"
     if dm_first == 0:
@@ -305,9 +322,33 @@ def check_search_brute(search_row, seed=0):
         assert got[1:] == ref[1:], (S, got, ref)
 
 
+def check_search_ties(search_row):
+    """The tie rule of the definition: among equal S/N, the smaller width, then
+    the earlier start.  Integer centred values keep every boxcar sum exact, so
+    the ties below are exact in binary64.
+
+    * Two identical spikes (mean 1, centred values 31 and -1): the first wins.
+    * A width-4 boxcar of 3s starting at 5 and a width-1 spike of 6 at 20 (mean
+      0): 12 / (2 sigma) and 6 / sigma are the same binary64 number, and the
+      smaller width wins although it starts later."""
+    y = np.zeros(64)
+    y[12] = y[40] = 32.0
+    snr, t, w = search_row(y, 6)
+    assert (t, w) == (12, 1), (t, w)
+    y = np.zeros(64)
+    y[5:9] = 3.0
+    y[20] = 6.0
+    y[40:58] = -1.0
+    sigma = math.sqrt(90.0 / 64.0)
+    snr, t, w = search_row(y, 6)
+    assert snr == 6.0 / sigma, (snr, 6.0 / sigma)
+    assert (t, w) == (20, 1), (t, w)
+
+
 def run_search(search_row):
     check_search_spike(search_row)
     check_search_boxcar_pulse(search_row)
     check_search_affine_invariance(search_row)
     check_search_constant_row(search_row)
     check_search_brute(search_row)
+    check_search_ties(search_row)

@@ -26,6 +26,15 @@ def test_pins_on_small_plans():
     pins.run_all(oracle.default())
 
 
+def test_alg1_delays_exact_rational_and_equal_to_c_oracle():
+    """The pure-Python delay law against exact rational rounding, and against
+    the C oracle's table (two independent codings of Eq. (1))."""
+    from oracle import alg1
+    pins.check_alg1_delays(alg1.delays)
+    for args in pins.DELAY_ARGS + [synth.TINY.plan_args()[:7], synth.FD_SLICE.plan_args()[:7]]:
+        assert np.array_equal(np.array(alg1.delays(*args), dtype=np.int32), oracle.delay_table(*args)), args
+
+
 @pytest.mark.parametrize("setup", [synth.TINY, synth.APERTIF, synth.LOFAR, synth.FD_SLICE],
                          ids=lambda s: s.name)
 def test_delay_table_exact_rational(setup):

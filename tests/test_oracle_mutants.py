@@ -50,6 +50,37 @@ def test_mutant_is_caught(name, tmp_path):
         pins.run_all(mutant)
 
 
+# Planted mistakes in copies of the pure-Python delay law (oracle/alg1.py).
+ALG1_MUTANTS = {
+    "truncate_instead_of_round": ("row.append(int(round(seconds / t_samp)))", "row.append(int(seconds / t_samp))"),
+    "band_edge_reference": ("f_h = f_min + (n_channels - 1) * df", "f_h = f_min + n_channels * df"),
+    "dm_grid_off_by_one": ("        dm = dm_first + i * dm_step\n", "        dm = dm_first + (i + 1) * dm_step\n"),
+    "reversed_channels": ("            f = f_min + ch * df\n", "            f = f_min + (n_channels - 1 - ch) * df\n"),
+}
+
+
+def _mutated_module(path, old, new, name):
+    import types
+    src = open(path).read()
+    assert src.count(old) == 1, "mutation site not found exactly once"
+    mod = types.ModuleType(name)
+    exec(compile(src.replace(old, new), name + ".py", "exec"), mod.__dict__)
+    return mod
+
+
+def test_unmutated_alg1_delays_pass():
+    from oracle import alg1
+    pins.check_alg1_delays(alg1.delays)
+
+
+@pytest.mark.parametrize("name", sorted(ALG1_MUTANTS))
+def test_alg1_mutant_is_caught(name):
+    from oracle import alg1
+    mod = _mutated_module(alg1.__file__, *ALG1_MUTANTS[name], "alg1_mutant")
+    with pytest.raises(AssertionError):
+        pins.check_alg1_delays(mod.delays)
+
+
 # Planted mistakes in copies of the search oracle (oracle/search.py).
 SEARCH_MUTANTS = {
     "sample_std": ("return mu, np.sqrt(np.mean((y - mu) ** 2))",
@@ -61,6 +92,8 @@ SEARCH_MUTANTS = {
                           "s = (c[w:] - c[:-w]) / (sigma * np.sqrt(w)); s = np.roll(s, 1)"),
     "widths_skip_one": ("return [1 << k for k in range(n_widths) if (1 << k) <= n_samples]",
                         "return [1 << k for k in range(1, n_widths) if (1 << k) <= n_samples]"),
+    "ties_to_larger_width": ("if s[t] > best[0]:", "if s[t] >= best[0]:"),
+    "ties_to_later_start": ("t = int(np.argmax(s))", "t = len(s) - 1 - int(np.argmax(s[::-1]))"),
 }
 
 
@@ -71,12 +104,7 @@ def test_unmutated_search_oracle_passes():
 
 @pytest.mark.parametrize("name", sorted(SEARCH_MUTANTS))
 def test_search_mutant_is_caught(name):
-    import types
     from oracle import search
-    old, new = SEARCH_MUTANTS[name]
-    src = open(search.__file__).read()
-    assert src.count(old) == 1, "mutation site not found exactly once"
-    mod = types.ModuleType("search_mutant")
-    exec(compile(src.replace(old, new), "search_mutant.py", "exec"), mod.__dict__)
+    mod = _mutated_module(search.__file__, *SEARCH_MUTANTS[name], "search_mutant")
     with pytest.raises(AssertionError):
         pins.run_search(mod.search_row)
