@@ -97,6 +97,8 @@ def compulsory_bytes(setup, in_bytes_per_sample, plan):
 
 
 def timed(torch, fn, steps, warmup, stream):
+    """Back-to-back launches: mean ms per call over `steps` calls between two
+    HIP events on `stream` (caches stay warm between calls), and wall seconds."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -110,6 +112,42 @@ def timed(torch, fn, steps, warmup, stream):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return e0.elapsed_time(e1) / steps, wall
+
+
+FLUSH_BYTES = 1 << 30   # > the 256 MiB MALL: every timed call starts with cold caches
+_FLUSH = []
+
+
+def flush_caches(torch, stream):
+    """Write a 1 GiB scratch buffer on `stream` (evicts the MALL and L2)."""
+    if not _FLUSH:
+        _FLUSH.append(torch.empty(FLUSH_BYTES // 4, dtype=torch.float32, device="cuda"))
+    with torch.cuda.stream(stream):
+        _FLUSH[0].fill_(float(len(_FLUSH)))
+
+
+def timed_protocol(torch, fn, steps, warmup, stream):
+    """The measurement protocol: `warmup` untimed calls, then `steps` timed
+    calls, each after a 1 GiB scratch write and between its own pair of HIP
+    events on `stream` (the stream the library launches on).  Returns mean,
+    min and standard deviation of those per-call times, plus the back-to-back
+    mean (warm caches) as a second figure."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in ev:
+        flush_caches(torch, stream)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
+    warm, _ = timed(torch, fn, steps, 1, stream)
+    return dict(ms=float(per.mean()), ms_min=float(per.min()), ms_std=float(per.std()), ms_warm=warm,
+                wall_s=wall, reps=steps)
 
 
 def gpu_input(torch, setup, T, dtype, seed):
@@ -135,9 +173,9 @@ def measure_forward(torch, dd, setup, dtype, steps, warmup, stream, numpy_input=
     if tune:
         plan.autotune(dd.DD_FORWARD, code, reps=3)   # Sec. IV-A: tune, then measure
     plan.prepare(dd.DD_FORWARD, code)
-    ms, wall = timed(torch, lambda: dd.dedisperse(x, plan, out=out), steps, warmup, stream)
+    t = timed_protocol(torch, lambda: dd.dedisperse(x, plan, out=out), steps, warmup, stream)
     bpe = {"f32": 4, "f16": 2, "u8": 1}[dtype]
-    return dict(ms=ms, wall_s=wall, gflops=setup.adds / (ms * 1e-3) / 1e9,
+    return dict(t, gflops=setup.adds / (t["ms"] * 1e-3) / 1e9,
                 compulsory_bytes=compulsory_bytes(setup, bpe, plan), tile=plan.get_tile(dtype=code)), plan
 
 
@@ -150,8 +188,8 @@ def measure_adjoint(torch, dd, setup, steps, warmup, stream):
     g.manual_seed(setup.seed)
     gy = torch.randn((setup.n_dm, setup.n_samples), generator=g, device="cuda")
     gx = torch.empty((setup.n_channels, plan.input_samples), device="cuda")
-    ms, wall = timed(torch, lambda: dd.dedisperse_adjoint(gy, plan, out=gx), steps, warmup, stream)
-    return dict(ms=ms, wall_s=wall, gflops=setup.adds / (ms * 1e-3) / 1e9,
+    t = timed_protocol(torch, lambda: dd.dedisperse_adjoint(gy, plan, out=gx), steps, warmup, stream)
+    return dict(t, gflops=setup.adds / (t["ms"] * 1e-3) / 1e9,
                 compulsory_bytes=compulsory_bytes(setup, 4, plan), tile=plan.get_tile(direction=dd.DD_ADJOINT))
 
 
@@ -176,9 +214,33 @@ def cpu_baseline(setup, budget_s=12.0):
         reps += 1
     adds = reps * n_dm * setup.n_samples * setup.n_channels
     return {"value": adds / dt / 1e9, "unit": "GFLOP/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)),
             "sample": "%s input, first %d of %d trial DMs, all %d channels x %d samples, %d run(s) "
                       "(%.2e adds in %.1f s)" % (setup.name, n_dm, setup.n_dm, setup.n_channels,
                                                  setup.n_samples, reps, adds, dt)}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def copy_bandwidth(torch, stream, n_bytes=256 << 20, reps=10):
+    """Device-to-device copy of n_bytes (read + write 2 * n_bytes per copy):
+    the achievable HBM rate the kernels' traffic is compared with, and the
+    reference dispatch for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    src = torch.empty(n_bytes // 4, dtype=torch.float32, device="cuda").normal_()
+    dst = torch.empty_like(src)
+    t = timed_protocol(torch, lambda: dst.copy_(src), reps, 2, stream)
+    del src, dst
+    return dict(bytes_moved=2 * n_bytes, ms=t["ms"], GBps=2 * n_bytes / (t["ms"] * 1e-3) / 1e9,
+                ms_warm=t["ms_warm"])
 
 
 def realtime(torch, dd, stream, n_chunks):
@@ -215,43 +277,87 @@ def realtime(torch, dd, stream, n_chunks):
     return r
 
 
-def extras(torch, dd, stream, steps):
+EXTRAS = ("lofar_f32", "lofar_adjoint", "apertif_u8", "apertif_f16", "apertif_0dm", "lofar_0dm", "search_apertif",
+          "realtime_apertif_u8", "apertif_adjoint", "fwd_bwd_8beams", "batched64_u8", "batched64_f16")
+
+
+def extras(torch, dd, stream, steps, only=None):
+    """Secondary same-GPU measurements (names in EXTRAS; `only`: a subset)."""
+    want = (lambda name: True) if not only else (lambda name: name in only)
     res = {}
     # LOFAR-shaped beam, float32
-    r, _ = measure_forward(torch, dd, synth.LOFAR, "f32", steps, 2, stream)
-    r["hbm_GBps"] = r["compulsory_bytes"] / (r["ms"] * 1e-3) / 1e9
-    res["lofar_f32"] = r
-    log("lofar f32: %.3f ms %.1f GFLOP/s" % (r["ms"], r["gflops"]))
-    r = measure_adjoint(torch, dd, synth.LOFAR, steps, 2, stream)
-    res["lofar_adjoint"] = dict(ms=r["ms"], gflops=r["gflops"], tile=r["tile"])
-    log("lofar adjoint: %.3f ms (variant %d)" % (r["ms"], r["tile"]))
+    if want("lofar_f32"):
+        r, _ = measure_forward(torch, dd, synth.LOFAR, "f32", steps, 2, stream)
+        r["hbm_GBps"] = r["compulsory_bytes"] / (r["ms"] * 1e-3) / 1e9
+        res["lofar_f32"] = r
+        log("lofar f32: %.3f ms %.1f GFLOP/s (variant %d)" % (r["ms"], r["gflops"], r["tile"]))
+    if want("lofar_adjoint"):
+        r = measure_adjoint(torch, dd, synth.LOFAR, steps, 2, stream)
+        res["lofar_adjoint"] = r
+        log("lofar adjoint: %.3f ms (variant %d)" % (r["ms"], r["tile"]))
     # low precision storage, Apertif
     for dt in ("u8", "f16"):
-        r, _ = measure_forward(torch, dd, synth.APERTIF, dt, steps, 2, stream)
-        res["apertif_" + dt] = r
-        log("apertif %s: %.3f ms %.1f GFLOP/s" % (dt, r["ms"], r["gflops"]))
+        if want("apertif_" + dt):
+            r, _ = measure_forward(torch, dd, synth.APERTIF, dt, steps, 2, stream)
+            res["apertif_" + dt] = r
+            log("apertif %s: %.3f ms %.1f GFLOP/s (variant %d)" % (dt, r["ms"], r["gflops"], r["tile"]))
     # perfect-reuse limit (Sec. IV-C / V-C): every trial DM is 0, tuned again
     for base in (synth.APERTIF, synth.LOFAR):
         z = dataclasses.replace(base, name=base.name + "_0dm", dm_step=0.0)
-        r, _ = measure_forward(torch, dd, z, "f32", steps, 2, stream)
-        res[z.name] = r
-        log("%s: %.3f ms %.1f GFLOP/s (variant %d)" % (z.name, r["ms"], r["gflops"], r["tile"]))
+        if want(z.name):
+            r, _ = measure_forward(torch, dd, z, "f32", steps, 2, stream)
+            res[z.name] = r
+            log("%s: %.3f ms %.1f GFLOP/s (variant %d)" % (z.name, r["ms"], r["gflops"], r["tile"]))
     # candidate search over the dedispersed Apertif rows (boxcars of 1 .. 1,024 samples)
-    sp = dd.Plan.from_setup(synth.APERTIF)
-    sy = dd.dedisperse(gpu_input(torch, synth.APERTIF, sp.input_samples, "f32", synth.APERTIF.seed), sp)
-    ms_s, _ = timed(torch, lambda: dd.search_boxcar(sy, n_widths=11), steps, 2, stream)
-    res["search_apertif"] = dict(ms=ms_s, n_widths=11, rows_bytes=sy.numel() * 4,
-                                 rows_GBps=sy.numel() * 4 / (ms_s * 1e-3) / 1e9)
-    log("search apertif (11 widths): %.3f ms, %.0f GB/s of rows" % (ms_s, res["search_apertif"]["rows_GBps"]))
-    del sy
+    if want("search_apertif"):
+        sp = dd.Plan.from_setup(synth.APERTIF)
+        sy = dd.dedisperse(gpu_input(torch, synth.APERTIF, sp.input_samples, "f32", synth.APERTIF.seed), sp)
+        t = timed_protocol(torch, lambda: dd.search_boxcar(sy, n_widths=11), steps, 2, stream)
+        ms_s = t["ms"]
+        res["search_apertif"] = dict(t, n_widths=11, rows_bytes=sy.numel() * 4,
+                                     rows_GBps=sy.numel() * 4 / (ms_s * 1e-3) / 1e9)
+        log("search apertif (11 widths): %.3f ms, %.0f GB/s of rows" % (ms_s, res["search_apertif"]["rows_GBps"]))
+        del sy
     # streaming: one Apertif beam fed second by second from pinned host memory
-    res["realtime_apertif_u8"] = realtime(torch, dd, stream, max(10, steps // 2))
+    if want("realtime_apertif_u8"):
+        res["realtime_apertif_u8"] = realtime(torch, dd, stream, max(10, steps // 2))
     # adjoint and fwd+bwd (8 Apertif-shaped beams through autograd)
+    if want("apertif_adjoint") or want("fwd_bwd_8beams"):
+        res.update(fwd_bwd(torch, dd, stream, steps, want))
+    # batched: 64 uneven beams, one graph launch (one kernel per tile variant in use)
+    for dt, code in (("u8", dd.DD_U8), ("f16", dd.DD_F16)):
+        if not want("batched64_" + dt):
+            continue
+        beams = synth.batched_beams()
+        plans = [dd.Plan.from_setup(b) for b in beams]
+        xs = [gpu_input(torch, b, p.input_samples, dt, b.seed) for b, p in zip(beams, plans)]
+        outs = [torch.empty((b.n_dm, b.n_samples), device="cuda") for b in beams]
+        batch = dd.Batch(plans, dtype=code, tune=True, reps=1)
+        ms_b, _ = timed(torch, lambda: batch.run(xs, outs), max(2, steps // 4), 1, stream)
+
+        # same beams one plain launch each (same storage type)
+        def singles():
+            for x, p, o in zip(xs, plans, outs):
+                dd.dedisperse(x, p, out=o)
+        ms_s, _ = timed(torch, singles, max(2, steps // 4), 1, stream)
+        res["batched64_" + dt] = dict(ms=ms_b, gflops=batch.adds / (ms_b * 1e-3) / 1e9,
+                                      per_beam_launches_ms=ms_s, speedup_over_per_beam=ms_s / ms_b,
+                                      adds=batch.adds, variants=sorted(set(batch.variants())),
+                                      kernels_in_graph=len(set(batch.variants())),
+                                      note="back-to-back graph launches (each writes 14.5 GB of outputs)")
+        log("batched %s: %.3f ms (%.1f GFLOP/s), per-beam launches %.3f ms, variants %s"
+            % (dt, ms_b, batch.adds / (ms_b * 1e-3) / 1e9, ms_s, sorted(set(batch.variants()))))
+        del xs, outs, batch
+        torch.cuda.empty_cache()
+    return res
+
+
+def fwd_bwd(torch, dd, stream, steps, want):
+    """The Apertif adjoint alone, and fwd+bwd of 8 Apertif-shaped beams
+    through autograd (loss sum w * out^2)."""
+    res = {}
     beams = synth.fwd_bwd_beams()
     plans = [dd.Plan.from_setup(b) for b in beams]
-    xs = [gpu_input(torch, b, p.input_samples, "f32", b.seed).requires_grad_(True) for b, p in zip(beams, plans)]
-    ws = [torch.rand((b.n_dm, b.n_samples), device="cuda", generator=torch.Generator(device="cuda").manual_seed(b.seed + 1))
-          for b in beams]
     import tempfile
     with tempfile.TemporaryDirectory() as tmp:
         cache = os.path.join(tmp, "tune.txt")   # the 8 beams share one shape: tune once
@@ -260,19 +366,28 @@ def extras(torch, dd, stream, steps):
             p.autotune(dd.DD_ADJOINT, dd.DD_F32, reps=3, cache_path=cache)
             p.prepare(dd.DD_FORWARD, dd.DD_F32)
             p.prepare(dd.DD_ADJOINT, dd.DD_F32)
-    gy = torch.randn((beams[0].n_dm, beams[0].n_samples), device="cuda")
-    ms_adj, _ = timed(torch, lambda: dd.dedisperse_adjoint(gy, plans[0]), steps, 2, stream)
-    res["apertif_adjoint"] = dict(ms=ms_adj, gflops=beams[0].adds / (ms_adj * 1e-3) / 1e9,
-                                  tile=plans[0].get_tile(direction=dd.DD_ADJOINT))
-    log("apertif adjoint: %.3f ms" % ms_adj)
+    if want("apertif_adjoint"):
+        gy = torch.randn((beams[0].n_dm, beams[0].n_samples), device="cuda")
+        gx0 = torch.empty((beams[0].n_channels, plans[0].input_samples), device="cuda")
+        t = timed_protocol(torch, lambda: dd.dedisperse_adjoint(gy, plans[0], out=gx0), steps, 2, stream)
+        ms_adj = t["ms"]
+        res["apertif_adjoint"] = dict(t, gflops=beams[0].adds / (ms_adj * 1e-3) / 1e9,
+                                      tile=plans[0].get_tile(direction=dd.DD_ADJOINT))
+        del gx0, gy
+        log("apertif adjoint: %.3f ms (variant %d)" % (ms_adj, res["apertif_adjoint"]["tile"]))
+    if not want("fwd_bwd_8beams"):
+        return res
+    xs = [gpu_input(torch, b, p.input_samples, "f32", b.seed).requires_grad_(True) for b, p in zip(beams, plans)]
+    ws = [torch.rand((b.n_dm, b.n_samples), device="cuda",
+                     generator=torch.Generator(device="cuda").manual_seed(b.seed + 1)) for b in beams]
 
-    def fwd_bwd():
+    def step():
         for x, p, w in zip(xs, plans, ws):
             x.grad = None
             y = dd.Dedisperse.apply(x, p)
             (w * y * y).sum().backward()
 
-    ms_fb, _ = timed(torch, fwd_bwd, max(2, steps // 4), 1, stream)
+    ms_fb, _ = timed(torch, step, max(2, steps // 4), 1, stream)
     with torch.no_grad():
         ms_f8, _ = timed(torch, lambda: [dd.dedisperse(x, p) for x, p in zip(xs, plans)], max(2, steps // 4), 1,
                          stream)
@@ -280,29 +395,11 @@ def extras(torch, dd, stream, steps):
     res["fwd_bwd_8beams"] = dict(ms=ms_fb, gflops=adds_fb / (ms_fb * 1e-3) / 1e9, forward_only_ms=ms_f8,
                                  over_forward_only=ms_fb / ms_f8,
                                  note="forward + adjoint adds of 8 beams per step, autograd incl. loss ops; "
-                                      "forward_only_ms: the same 8 forwards without autograd")
+                                      "forward_only_ms: the same 8 forwards without autograd; back-to-back "
+                                      "steps (each step moves ~4 GB, far more than the caches hold)")
     log("fwd+bwd 8 beams: %.3f ms (forward only %.3f ms, x%.2f)" % (ms_fb, ms_f8, ms_fb / ms_f8))
-    del xs, ws, gy
-    # batched: 64 uneven beams, one graph launch (one kernel per tile variant in use)
-    for dt, code in (("u8", dd.DD_U8), ("f16", dd.DD_F16)):
-        beams = synth.batched_beams()
-        plans = [dd.Plan.from_setup(b) for b in beams]
-        xs = [gpu_input(torch, b, p.input_samples, dt, b.seed) for b, p in zip(beams, plans)]
-        outs = [torch.empty((b.n_dm, b.n_samples), device="cuda") for b in beams]
-        batch = dd.Batch(plans, dtype=code, tune=True, reps=1)
-        ms_b, _ = timed(torch, lambda: batch.run(xs, outs), max(2, steps // 4), 1, stream)
-        # same beams one plain launch each (same storage type)
-        def singles():
-            for x, p, o in zip(xs, plans, outs):
-                dd.dedisperse(x, p, out=o)
-        ms_s, _ = timed(torch, singles, max(2, steps // 4), 1, stream)
-        res["batched64_" + dt] = dict(ms=ms_b, gflops=batch.adds / (ms_b * 1e-3) / 1e9,
-                                      per_beam_launches_ms=ms_s, speedup_over_per_beam=ms_s / ms_b,
-                                      adds=batch.adds,
-                                      kernels_in_graph=len(set(batch.variants())))
-        log("batched %s: %.3f ms (%.1f GFLOP/s), per-beam launches %.3f ms" % (dt, ms_b, batch.adds / (ms_b * 1e-3) / 1e9, ms_s))
-        del xs, outs, batch
-        torch.cuda.empty_cache()
+    del xs, ws
+    torch.cuda.empty_cache()
     return res
 
 
@@ -362,6 +459,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="apertif", choices=["apertif", "lofar"])
     ap.add_argument("--no-extra", action="store_true")
+    ap.add_argument("--extras", metavar="NAMES",
+                    help="comma-separated subset of the extras (%s)" % ", ".join(EXTRAS))
     ap.add_argument("--adjoint", action="store_true",
                     help="time the adjoint of the workload in the headline slot (for its profile)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -370,7 +469,7 @@ def main():
     ap.add_argument("--tune-study", metavar="JSON",
                     help="run the auto-tuning study over 2..4096 DMs for both setups, write it here, exit")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a plain 256 MiB device copy (scale for HBM byte counters)")
+                    help="accepted for older profile commands: the 256 MiB copy always runs")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: beams are independent, so several GPUs would each run their own "
@@ -438,15 +537,20 @@ def main():
         "paper_context": {"hd7970_2000dms_s": 0.106, "hd7970_GFLOPs": round(2000 * 1024 * 20000 / 0.106 / 1e9, 1),
                           "note": "AMD HD7970, OpenCL, 2,000 DMs x 1 s Apertif (Sec. V-D); other hardware"},
     }
-    if args.calibrate_copy:
-        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").normal_()
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    line["timing"] = {"protocol": "%d untimed calls, then %d timed calls, each after a 1 GiB scratch write, "
+                                  "between its own HIP events on the launch stream" % (args.warmup, args.steps),
+                      "ms_mean": round(ms, 5), "ms_min": round(r["ms_min"], 5), "ms_std": round(r["ms_std"], 5),
+                      "ms_warm_back_to_back": round(r["ms_warm"], 5)}
+    cb = copy_bandwidth(torch, stream)
+    line["hbm"].update(measured_copy_GBps=round(cb["GBps"], 1),
+                       frac_of_measured_copy=round(hbm_gbps / cb["GBps"], 4),
+                       copy_note="256 MiB device-to-device copy, 512 MiB moved per copy, same protocol")
+    log("copy: %.1f GB/s" % cb["GBps"])
     if not args.no_extra:
-        line["extras"] = extras(torch, dd, stream, max(5, args.steps // 5))
+        only = set(args.extras.split(",")) if args.extras else None
+        if only and not only <= set(EXTRAS):
+            raise SystemExit("unknown extras: %s" % sorted(only - set(EXTRAS)))
+        line["extras"] = extras(torch, dd, stream, max(5, args.steps // 5), only)
     if not args.no_cpu_baseline:
         log("cpu baseline (FP64 oracle) ...")
         line["cpu_baseline"] = cpu_baseline(setup)

@@ -134,10 +134,21 @@ def _check_input(x, plan: Plan):
         raise TypeError("input must be a GPU tensor")
     if x.dim() != 2 or x.shape[0] != plan.n_channels:
         raise ValueError("input must be [n_channels][>= input_samples]")
-    if x.stride(1) != 1:
-        raise ValueError("input rows must be contiguous")
+    if x.stride(1) != 1 or x.stride(0) < plan.input_samples:
+        raise ValueError("input rows must be contiguous and must not overlap")
     if x.shape[1] < plan.input_samples:
         raise ValueError("input rows hold %d samples, the plan needs %d" % (x.shape[1], plan.input_samples))
+
+
+def _check_output(out, plan: Plan, device):
+    """out must be float32 [n_dm][>= n_samples], unit column stride, on `device`."""
+    torch = _torch()
+    if not isinstance(out, torch.Tensor):
+        raise TypeError("out must be a tensor")
+    if (out.dtype != torch.float32 or out.device != device or out.dim() != 2
+            or out.shape[0] != plan.n_dm or out.shape[1] < plan.n_samples or out.stride(1) != 1
+            or out.stride(0) < plan.n_samples):
+        raise ValueError("out must be float32 [n_dm][>= n_samples] with unit column stride on %s" % device)
 
 
 def dedisperse(x, plan: Plan, out=None):
@@ -146,9 +157,8 @@ def dedisperse(x, plan: Plan, out=None):
     _check_input(x, plan)
     if out is None:
         out = torch.empty((plan.n_dm, plan.n_samples), dtype=torch.float32, device=x.device)
-    elif (out.dtype != torch.float32 or out.device != x.device or out.dim() != 2
-          or out.shape[0] != plan.n_dm or out.shape[1] < plan.n_samples or out.stride(1) != 1):
-        raise ValueError("out must be float32 [n_dm][>= n_samples] on the input's device")
+    else:
+        _check_output(out, plan, x.device)
     with torch.cuda.device(x.device):
         check(_lib.lib().dd_dedisperse(plan.handle, ctypes.c_void_p(x.data_ptr()), _dtype_code(x.dtype),
                                        x.stride(0), ctypes.c_void_p(out.data_ptr()), out.stride(0),
@@ -251,9 +261,16 @@ class Batch:
             _check_input(x, p)
             if x.dtype != code:
                 raise TypeError("batch inputs must all be %s" % code)
+            if x.device != xs[0].device:
+                raise ValueError("batch inputs must all be on one device")
         if outs is None:
             outs = [torch.empty((p.n_dm, p.n_samples), dtype=torch.float32, device=xs[0].device)
                     for p in self.plans]
+        else:
+            if len(outs) != n:
+                raise ValueError("one output per beam")
+            for o, p in zip(outs, self.plans):
+                _check_output(o, p, xs[0].device)
         ins = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
         ins_s = (ctypes.c_int64 * n)(*[x.stride(0) for x in xs])
         os_ = (ctypes.c_void_p * n)(*[o.data_ptr() for o in outs])
@@ -316,9 +333,8 @@ class Realtime:
             raise ValueError("chunk must be [n_channels][>= n_samples] with unit column stride")
         if out is None:
             out = torch.empty((p.n_dm, p.n_samples), dtype=torch.float32, device=self.device)
-        if out.dtype != torch.float32 or out.device != self.device or out.dim() != 2 or out.stride(1) != 1 \
-                or out.shape[0] != p.n_dm or out.shape[1] < p.n_samples:
-            raise ValueError("out must be float32 [n_dm][>= n_samples] on the object's device")
+        else:
+            _check_output(out, p, self.device)
         with torch.cuda.device(self.device):
             check(_lib.lib().dd_realtime_push(self._h, ctypes.c_void_p(chunk.data_ptr()), chunk.stride(0),
                                               ctypes.c_void_p(out.data_ptr()), out.stride(0)))

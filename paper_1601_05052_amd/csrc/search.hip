@@ -144,7 +144,9 @@ __global__ __launch_bounds__(kSearchThreads) void boxcar_search_kernel(const flo
             constexpr int kPer = (kExt + kSearchThreads - 1) / kSearchThreads;
             static_assert(kChunk % kSearchThreads == 0, "chunk starts split evenly over the threads");
             for (int32_t w = 1;; w *= 2) {
-                const float scale = inv_sigma * rsqrtf(static_cast<float>(w));
+                // 1/sqrt(w) correctly rounded (exact for even powers of two),
+                // so boxcars whose binary64 S/N tie also tie here.
+                const float scale = inv_sigma * static_cast<float>(1.0 / sqrt(static_cast<double>(w)));
                 const bool last = w >= wmax;
                 float nv[kPer];
 #pragma unroll

@@ -9,6 +9,8 @@
 
 #include <cstdint>
 
+#include "srs_dims.h"
+
 namespace dd {
 namespace dev {
 
@@ -27,18 +29,6 @@ __device__ __forceinline__ float to_f32<uint8_t>(uint8_t v) { return static_cast
 typedef const __attribute__((address_space(4))) int32_t ctab;
 __device__ __forceinline__ ctab *as_ctab(const int32_t *p) { return (ctab *)reinterpret_cast<uintptr_t>(p); }
 
-struct SrsDims {
-    int64_t in_stride;
-    int64_t in_valid;
-    int64_t out_stride;
-    int64_t n_t;
-    int32_t n_acc;
-    int32_t n_rows;
-    int32_t wcap;
-    int32_t rows_per_chunk;
-    int32_t n_t_tiles;
-    int32_t n_acc_tiles;
-};
 
 // Map the hardware work-group id to (time tile, accumulator tile).  Work-groups
 // are dealt round-robin to the 8 XCDs; renumber so that each XCD receives a

@@ -3,7 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
-#include "srs_tile.h"
+#include "srs_dims.h"
 #include "srs_variants.def"
 
 namespace dd {

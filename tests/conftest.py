@@ -17,3 +17,11 @@ def pytest_configure(config):
 def gpu_available():
     import torch
     return torch.cuda.is_available()
+
+
+def pytest_sessionfinish(session, exitstatus):
+    path = os.environ.get("DD_ERROR_REPORT")
+    if path:
+        from tests import errors
+        if errors.RECORDS:
+            errors.write(path)

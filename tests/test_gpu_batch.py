@@ -44,10 +44,10 @@ def test_batch_matches_oracle_and_single_beam(dtype, code):
         yh = to_host(y)
         ref = oracle.dedisperse(x, table, b.n_samples)
         if dtype == "u8":
-            gates.exact(yh, ref, what=b.name)
+            gates.exact(yh, ref, what=b.name, report="batched small beams u8")
         else:
             absref = oracle.dedisperse(np.abs(x.astype(np.float64)), table, b.n_samples)
-            gates.gate(yh, ref, absref, what=b.name)
+            gates.gate(yh, ref, absref, what=b.name, report="batched small beams %s" % dtype)
         single = to_host(dedisperse(to_dev(x), p))
         assert np.array_equal(single, yh), b.name
 
@@ -109,7 +109,67 @@ def test_batched_workload_sampled_u8():
         table = oracle.delay_table(*b.plan_args()[:7])
         i, t = sample_points(b.n_dm, b.n_samples, 400, b.seed)
         yh = y[torch.from_numpy(i).long().cuda(), torch.from_numpy(t).long().cuda()].cpu().numpy()
-        gates.exact(yh, oracle.dedisperse_points(x, table, i, t), what=b.name)
+        gates.exact(yh, oracle.dedisperse_points(x, table, i, t), what=b.name,
+                    report="batched 64 beams u8, cost-model tiles (per-beam sampled outputs)")
+
+
+@pytest.mark.parametrize("dtype,code", [("u8", DD_U8), ("f16", DD_F16)])
+def test_batched_workload_tuned_sampled(dtype, code):
+    """The configuration the benchmark times: the 64-beam batch built with
+    per-beam tuning (Batch(..., tune=True, reps=1)) for u8 and f16 storage.
+    Every beam's sampled outputs against the oracle on the stored values: u8
+    bit for bit, f16 within the binary32 gates; errors reported per beam."""
+    torch = torch_mod()
+    beams = synth.batched_beams()
+    plans = [Plan.from_setup(b) for b in beams]
+    gen = {"u8": synth.noise_u8, "f16": synth.noise_f16}[dtype]
+    xs_h = [gen(b.n_channels, p.input_samples, b.seed) for b, p in zip(beams, plans)]
+    xs = [to_dev(x) for x in xs_h]
+    batch = Batch(plans, dtype=code, tune=True, reps=1)
+    assert batch.variants() == [p.get_tile(dtype=code) for p in plans]
+    outs = [torch.full((b.n_dm, b.n_samples), float("nan"), device="cuda") for b in beams]
+    batch.run(xs, outs)
+    torch.cuda.synchronize()
+    cfg = "batched 64 beams %s, tuned (per-beam sampled outputs)" % dtype
+    for b, x, y in zip(beams, xs_h, outs):
+        table = oracle.delay_table(*b.plan_args()[:7])
+        i, t = sample_points(b.n_dm, b.n_samples, 400, b.seed + 1)
+        yh = y[torch.from_numpy(i).long().cuda(), torch.from_numpy(t).long().cuda()].cpu().numpy()
+        ref = oracle.dedisperse_points(x, table, i, t)
+        if dtype == "u8":
+            gates.exact(yh, ref, what=b.name, report=cfg)
+        else:
+            absref = oracle.dedisperse_points(np.abs(x.astype(np.float64)), table, i, t)
+            gates.gate(yh, ref, absref, what=b.name, report=cfg + " vs f16 values")
+    del xs, outs, batch
+    torch.cuda.empty_cache()
+
+
+def test_batch_run_rejects_bad_outputs_before_launch():
+    """Outputs of the wrong dtype, shape, stride or count raise before any
+    launch, and the caller's buffers are left untouched."""
+    torch = torch_mod()
+    beams = small_beams()[:2]
+    plans = [Plan.from_setup(b) for b in beams]
+    batch = Batch(plans)
+    xs = [to_dev(synth.integers_f32(b.n_channels, p.input_samples, seed=3)) for b, p in zip(beams, plans)]
+    good = [torch.full((b.n_dm, b.n_samples), float("nan"), device="cuda") for b in beams]
+    bad_sets = [
+        [good[0], torch.full((beams[1].n_dm, beams[1].n_samples), float("nan"), device="cuda",
+                             dtype=torch.float16)],
+        [good[0], torch.full((beams[1].n_dm - 1, beams[1].n_samples), float("nan"), device="cuda")],
+        [good[0], torch.full((beams[1].n_dm, beams[1].n_samples - 1), float("nan"), device="cuda")],
+        [good[0], torch.full((beams[1].n_samples, beams[1].n_dm), float("nan"), device="cuda").t()],
+        [good[0]],
+        [good[0], torch.full((beams[1].n_dm, beams[1].n_samples), float("nan"))],   # host tensor
+    ]
+    for outs in bad_sets:
+        with pytest.raises((ValueError, TypeError)):
+            batch.run(xs, outs)
+    torch.cuda.synchronize()
+    assert all(bool(torch.isnan(o).all()) for o in good)
+    with pytest.raises((ValueError, TypeError)):
+        batch.run([xs[0], xs[1].cpu()], good)
 
 
 def test_batch_autotune_uses_tuned_tiles_and_stays_exact():

@@ -122,3 +122,21 @@ def test_apertif_beam_sampled_rows():
     check_rows(y, s.n_samples, 11, snr, t, w, rows=rows)
     for i in pulse_rows:
         assert snr[i] > np.median(snr) + 5, (i, snr[i])
+
+
+def test_tie_rule_smaller_width_then_earlier_start():
+    """Exact ties (every sum below is exact in binary32 and binary64): two
+    identical spikes give the earlier start; a width-4 boxcar of 3s and a later
+    width-1 spike of 6 (mean 0) have the same S/N and the smaller width wins."""
+    y = np.zeros((2, 64), dtype=np.float32)
+    y[0, 12] = y[0, 40] = 32.0
+    y[1, 5:9] = 3.0
+    y[1, 20] = 6.0
+    y[1, 40:58] = -1.0
+    snr, t, w = run(y, 64, 6)
+    assert (int(t[0]), int(w[0])) == (12, 1), (t[0], w[0])
+    assert (int(t[1]), int(w[1])) == (20, 1), (t[1], w[1])
+    for r in range(2):
+        ref = osearch.search_row(y[r], 6)
+        assert (int(t[r]), int(w[r])) == ref[1:], (r, ref)
+    check_rows(y, 64, 6, snr, t, w)

@@ -234,3 +234,28 @@ def test_one_hip_runtime_in_process():
     hsa = {l.split()[-1] for l in maps if "libhsa-runtime64" in l}
     assert len(hip) == 1, hip
     assert len(hsa) == 1, hsa
+
+
+def test_output_checks_reject_bad_outs_on_the_host():
+    """The binding checks every caller-supplied output (dtype, shape, strides,
+    device) before it hands pointers to the library; shown here on host
+    tensors, where no launch can happen."""
+    import torch
+    from paper_1601_05052_amd import _check_output
+    p = Plan(4, 1400.0, 1.0, 1e-4, 0.0, 1.0, 3, 10)
+    cpu = torch.device("cpu")
+    _check_output(torch.empty((3, 10)), p, cpu)
+    _check_output(torch.empty((3, 16))[:, :12], p, cpu)
+    bad = [torch.empty((3, 10), dtype=torch.float16),   # wrong dtype
+           torch.empty((2, 10)),                         # too few rows
+           torch.empty((3, 9)),                          # rows too short
+           torch.empty((10, 3)).t(),                     # non-unit column stride
+           torch.empty((3, 10, 1)),                      # not 2-D
+           torch.empty(30).as_strided((3, 10), (5, 1))]  # overlapping rows
+    for o in bad:
+        with pytest.raises(ValueError):
+            _check_output(o, p, cpu)
+    with pytest.raises(ValueError):
+        _check_output(torch.empty((3, 10)), p, torch.device("meta"))
+    with pytest.raises(TypeError):
+        _check_output(np.zeros((3, 10), np.float32), p, cpu)
