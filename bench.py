@@ -127,14 +127,12 @@ def flush_caches(torch, stream):
 
 
 def timed_protocol(torch, fn, steps, warmup, stream):
-    """The measurement protocol: `warmup` untimed calls, then `steps` timed
-    calls, each after a 1 GiB scratch write and between its own pair of HIP
-    events on `stream` (the stream the library launches on).  Returns mean,
-    min and standard deviation of those per-call times, plus the back-to-back
-    mean (warm caches) as a second figure."""
-    for _ in range(warmup):
-        fn()
-    torch.cuda.synchronize()
+    """The measurement protocol: `warmup` untimed calls, `steps` back-to-back
+    calls (warm caches; their mean is reported as a second figure), then
+    `steps` timed calls, each after a 1 GiB scratch write and between its own
+    pair of HIP events on `stream` (the stream the library launches on).
+    Returns mean, min and standard deviation of those per-call times."""
+    warm, _ = timed(torch, fn, steps, warmup, stream)   # warm-up calls, then the back-to-back figure
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
     for e0, e1 in ev:
@@ -145,7 +143,6 @@ def timed_protocol(torch, fn, steps, warmup, stream):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     per = np.array([e0.elapsed_time(e1) for e0, e1 in ev])
-    warm, _ = timed(torch, fn, steps, 1, stream)
     return dict(ms=float(per.mean()), ms_min=float(per.min()), ms_std=float(per.std()), ms_warm=warm,
                 wall_s=wall, reps=steps)
 
@@ -467,7 +464,8 @@ def main():
     ap.add_argument("--realtime", action="store_true",
                     help="only the streaming measurement (Apertif u8 chunks from pinned host memory), one JSON line")
     ap.add_argument("--tune-study", metavar="JSON",
-                    help="run the auto-tuning study over 2..4096 DMs for both setups, write it here, exit")
+                    help="run the auto-tuning study over 2..4096 DMs for both setups, write it here, exit "
+                         "(over the study library's grid when DEDISP_LIBRARY names it)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="accepted for older profile commands: the 256 MiB copy always runs")
     args = ap.parse_args()
@@ -488,7 +486,8 @@ def main():
     if args.tune_study:
         study = tune_study(torch, dd, stream)
         with open(args.tune_study, "w") as f:
-            json.dump(study, f, indent=1)
+            json.dump({"library": os.path.basename(os.environ.get("DEDISP_LIBRARY") or "libdedisp.so"),
+                       "variants": [list(v) for v in dd.tile_variants()], "instances": study}, f, indent=1)
         return
 
     # Headline input: the seeded workload with its pulses (arrivals from the
@@ -537,8 +536,9 @@ def main():
         "paper_context": {"hd7970_2000dms_s": 0.106, "hd7970_GFLOPs": round(2000 * 1024 * 20000 / 0.106 / 1e9, 1),
                           "note": "AMD HD7970, OpenCL, 2,000 DMs x 1 s Apertif (Sec. V-D); other hardware"},
     }
-    line["timing"] = {"protocol": "%d untimed calls, then %d timed calls, each after a 1 GiB scratch write, "
-                                  "between its own HIP events on the launch stream" % (args.warmup, args.steps),
+    line["timing"] = {"protocol": "%d untimed calls, %d back-to-back calls (ms_warm_back_to_back), then %d timed "
+                                  "calls, each after a 1 GiB scratch write, between its own HIP events on the "
+                                  "launch stream" % (args.warmup, args.steps, args.steps),
                       "ms_mean": round(ms, 5), "ms_min": round(r["ms_min"], 5), "ms_std": round(r["ms_std"], 5),
                       "ms_warm_back_to_back": round(r["ms_warm"], 5)}
     cb = copy_bandwidth(torch, stream)

@@ -23,7 +23,8 @@ import numpy as np
 from . import _lib
 from ._lib import DD_ADJOINT, DD_F16, DD_F32, DD_FORWARD, DD_U8, DedispError, check  # noqa: F401
 
-__all__ = ["Plan", "Batch", "Realtime", "search_boxcar", "Dedisperse", "dedisperse", "dedisperse_adjoint", "DedispError",
+__all__ = ["Plan", "Batch", "Realtime", "search_boxcar", "Dedisperse", "dedisperse", "dedisperse_adjoint",
+           "DedispError",
            "tile_variants", "DD_F32", "DD_F16", "DD_U8", "DD_FORWARD", "DD_ADJOINT"]
 
 

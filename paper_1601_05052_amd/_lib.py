@@ -73,12 +73,13 @@ def _load_torch_runtime() -> None:
 
 
 def lib():
-    """Load the in-tree libdedisp.so.  Raises ImportError if it is not built:
+    """Load the in-tree libdedisp.so (or the library DEDISP_LIBRARY names, e.g.
+    the auto-tuning study's build).  Raises ImportError if it is not built:
     there is no fallback implementation."""
     global _LIB
     if _LIB is None:
         _load_torch_runtime()
-        path = library_path()
+        path = os.environ.get("DEDISP_LIBRARY") or library_path()
         if not os.path.exists(path):
             raise ImportError("libdedisp.so is not built (%s); run: python -m paper_1601_05052_amd.build"
                               % path)

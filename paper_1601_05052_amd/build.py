@@ -1,6 +1,7 @@
 """Build libdedisp.so in-tree for gfx950 with hipcc.
 
     python -m paper_1601_05052_amd.build [-v]
+    python -m paper_1601_05052_amd.build --study [-v]   # auto-tuning study library
 
 Flags:
   --offload-arch=gfx950        CDNA4 only; no other targets, no CUDA path
@@ -84,6 +85,44 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     return lib
 
 
+STUDY_LIB_NAME = "libdedisp_study.so"
+
+
+def study_library_path() -> str:
+    return os.path.join(PKG, STUDY_LIB_NAME)
+
+
+def build_study(verbose: bool = False, jobs: int = 8) -> str:
+    """The auto-tuning study's library (Sec. IV-A): the same sources compiled
+    with -DDD_STUDY over the generated variant grid (csrc/gen_study.py),
+    float32 single-beam kernels only.  Not part of the product build."""
+    out_dir = os.path.join(PKG, "_build", "study")
+    sys.path.insert(0, CSRC)
+    import gen_study
+    n = gen_study.write(out_dir)
+    srcs = [p for p in sources() if not os.path.basename(p).startswith("srs_kernels_")]
+    srcs = sorted(glob.glob(os.path.join(out_dir, "study_kernels_*.hip"))) + srcs
+    objs, procs = [], []
+    for src in srcs:
+        obj = os.path.join(out_dir, os.path.basename(src) + ".o")
+        objs.append(obj)
+        cmd = [hipcc(), "-c", "-x", "hip"] + compile_flags() + ["-DDD_STUDY", "-I", out_dir, "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
+        if len(procs) >= jobs:
+            _wait(procs.pop(0), verbose)
+    for p in procs:
+        _wait(p, verbose)
+    lib = study_library_path()
+    tmp = lib + ".tmp%d" % os.getpid()
+    subprocess.run([hipcc(), "-shared", "--offload-arch=gfx950", "-o", tmp] + objs, check=True)
+    os.replace(tmp, lib)
+    if verbose:
+        print("%d study variants" % n)
+    return lib
+
+
 def _wait(item, verbose):
     src, proc = item
     out, _ = proc.communicate()
@@ -98,4 +137,7 @@ def _wait(item, verbose):
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--study" in sys.argv:
+        print(build_study(verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))

@@ -31,6 +31,8 @@ namespace dd {
 // Shared by the public calls and the tuner: checks done by the caller.
 int run_direction(const dd_plan *p, int direction, int32_t in_type, const Variant &v, const void *in,
                   int64_t in_stride, float *out, int64_t out_stride, hipStream_t stream) {
+    if (!has_kernel(v, direction == DD_FORWARD ? in_type : (int32_t)DD_F32))
+        return fail(DD_EUNSUPPORTED, "this library has no kernel of tile variant %d for this input type", v.id);
     SrsArgs a;
     int rc = make_args(p, direction, v, in, in_stride, out, out_stride, &a);
     if (rc != DD_OK)
@@ -41,13 +43,9 @@ int run_direction(const dd_plan *p, int direction, int32_t in_type, const Varian
     return DD_OK;
 }
 
-}  // namespace dd
-
-extern "C" {
-
-int dd_dedisperse(const dd_plan *p, const void *d_in, dd_dtype in_type, int64_t in_stride, float *d_out,
-                  int64_t out_stride, void *stream) {
-    clear_error();
+// Argument checks of the forward (shared with the allocation-free entry).
+int check_forward_args(const dd_plan *p, const void *d_in, int32_t in_type, int64_t in_stride, const float *d_out,
+                       int64_t out_stride) {
     if (!p)
         return fail(DD_EINVAL, "plan is NULL");
     if (!d_in || !d_out)
@@ -66,8 +64,21 @@ int dd_dedisperse(const dd_plan *p, const void *d_in, dd_dtype in_type, int64_t 
     const size_t out_bytes = (static_cast<size_t>(p->D - 1) * out_stride + p->S) * 4;
     if (overlaps(d_in, in_bytes, d_out, out_bytes))
         return fail(DD_ESHAPE, "input and output buffers overlap");
+    return DD_OK;
+}
+
+}  // namespace dd
+
+extern "C" {
+
+int dd_dedisperse(const dd_plan *p, const void *d_in, dd_dtype in_type, int64_t in_stride, float *d_out,
+                  int64_t out_stride, void *stream) {
+    clear_error();
+    int rc = check_forward_args(p, d_in, in_type, in_stride, d_out, out_stride);
+    if (rc != DD_OK)
+        return rc;
     const Variant *v = nullptr;
-    int rc = resolve_variant(p, DD_FORWARD, in_type, &v);
+    rc = resolve_variant(p, DD_FORWARD, in_type, &v);
     if (rc != DD_OK)
         return rc;
     return run_direction(p, DD_FORWARD, in_type, *v, d_in, in_stride, d_out, out_stride,
@@ -153,6 +164,9 @@ int dd_plan_set_tile(dd_plan *p, dd_direction direction, dd_dtype in_type, int32
         const Variant *v = find_variant(variant);
         if (!v)
             return fail(DD_EINVAL, "unknown tile variant %d", variant);
+        if (!has_kernel(*v, direction == DD_FORWARD ? (int32_t)in_type : (int32_t)DD_F32))
+            return fail(DD_EUNSUPPORTED, "this library has no kernel of tile variant %d for this input type",
+                        variant);
         if (!variant_fits(p, direction, *v))
             return fail(DD_EUNSUPPORTED, "tile variant %d cannot serve this plan (LDS window too large)",
                         variant);

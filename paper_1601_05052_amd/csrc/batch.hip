@@ -207,6 +207,10 @@ extern "C" int dd_batch_create(dd_batch **out, const dd_plan *const *plans, int3
         G.grid = static_cast<uint32_t>(gi.size());
         items.insert(items.end(), gi.begin(), gi.end());
         G.fn = multi_kernel(v, in_type);
+        if (!G.fn) {
+            batch_free(B);
+            return fail(DD_EUNSUPPORTED, "this library has no multi-beam kernel for tile variant %d", v.id);
+        }
         G.threads = static_cast<uint32_t>(64 * v.waves);
         for (int32_t b : G.beams)
             G.lds = std::max(G.lds, lds[b]);

@@ -207,8 +207,8 @@ def gen_config(it, tdw, nwr, acc0):
     return "\n".join(L)
 
 
-def render() -> str:
-    """The full text of regwin_asm.h."""
+def render(configs=None) -> str:
+    """The full text of regwin_asm.h (for CONFIGS, or the given configs)."""
     out = [
         "// GENERATED by gen_regwin_asm.py -- do not edit by hand.",
         "// Inline-assembly row step of the register-window kernel (gfx950).",
@@ -224,7 +224,7 @@ def render() -> str:
     for n in sorted({t for t in TUPLES if t > 2}):
         out.append("typedef float v%df __attribute__((ext_vector_type(%d)));" % (n, n))
     out += ["", "template <int IT, int TDW, int NWR>", "struct RegWin;", ""]
-    for cfg in CONFIGS:
+    for cfg in (CONFIGS if configs is None else configs):
         out.append(gen_config(*cfg))
         out.append("")
     out += ["}  // namespace dev", "}  // namespace dd", ""]

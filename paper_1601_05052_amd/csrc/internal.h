@@ -86,10 +86,22 @@ struct SrsDims;
 // Launcher of one variant for one input type (srs_launch.h).
 using LaunchFn = hipError_t (*)(const SrsArgs &, const dev::SrsDims &, uint32_t, size_t, hipStream_t);
 
+// One variant's launcher in a slice of the auto-tuning study's list (the
+// study library compiles its float32 kernels in slices, see gen_study.py).
+struct StudyEntry {
+    int32_t id;
+    LaunchFn fn;
+};
+
+// Whether this library holds the variant's single-beam kernel for in_type
+// (every variant and type in the product library; float32 only in the study
+// library).
+bool has_kernel(const Variant &v, int32_t in_type);
 // Launch one shifted-row-sum problem with the given variant.
 hipError_t launch_srs(const Variant &v, int32_t in_type, const SrsArgs &a, hipStream_t stream);
 // The variant's multi-beam kernel (arguments: BatchPtrs by value, const
-// BeamDesc *, const uint32_t *items; 64 * waves threads per work-group).
+// BeamDesc *, const uint32_t *items; 64 * waves threads per work-group), or
+// null where the library has none (the study library).
 const void *multi_kernel(const Variant &v, int32_t in_type);
 
 // Host-side layout of one (direction, variant) on one plan.
@@ -130,6 +142,9 @@ struct dd_plan {
     mutable std::mutex mu;
     // (device, direction, variant id) -> device tables
     mutable std::map<std::tuple<int, int, int>, dd::TileTables> tables;
+    // (direction, variant id) -> the same tables in host memory, kept once
+    // built (the allocation-free entry stages them into its own device array)
+    mutable std::map<std::pair<int, int>, dd::Layout> host_tables;
     // (direction, variant id) -> (feasible, wcap, rows per chunk), host only
     mutable std::map<std::pair<int, int>, std::tuple<bool, int32_t, int32_t>> fit;
     // forced tile per (direction, dtype); -1 = automatic
@@ -151,7 +166,7 @@ int32_t choose_variant(const dd_plan *p, int direction, int32_t in_type);
 // The variant a call uses: forced, else tuned, else the cost model's default.
 int32_t resolved_variant(const dd_plan *p, int direction, int32_t in_type);
 // Cost-model choice among `cand` (ids) that fit; -1 if none fits.
-int32_t best_by_model(const dd_plan *p, int direction, const int32_t *cand, int32_t n_cand);
+int32_t best_by_model(const dd_plan *p, int direction, int32_t in_type, const int32_t *cand, int32_t n_cand);
 // Time the candidates on the plan's own sizes (scratch buffers allocated
 // here); best id and mean ms.  Synchronises the stream.
 int tune_candidates(const dd_plan *p, int direction, int32_t in_type, int32_t reps, const int32_t *cand,
@@ -159,4 +174,13 @@ int tune_candidates(const dd_plan *p, int direction, int32_t in_type, int32_t re
 // Fill SrsArgs for one call (tables built on demand).
 int make_args(const dd_plan *p, int direction, const Variant &v, const void *in, int64_t in_stride,
               float *out, int64_t out_stride, SrsArgs *a);
+// The sizes and data pointers of SrsArgs for one call (no tables).
+void args_dims(const dd_plan *p, int direction, const void *in, int64_t in_stride, float *out, int64_t out_stride,
+               SrsArgs *a);
+// Host copy of the tables of (direction, variant), or null if no call has
+// built them yet (dd_plan_prepare or a first compute call does).
+const Layout *plan_host_layout(const dd_plan *p, int direction, int32_t variant);
+// Argument checks of the forward (api.cpp).
+int check_forward_args(const dd_plan *p, const void *d_in, int32_t in_type, int64_t in_stride, const float *d_out,
+                       int64_t out_stride);
 }  // namespace dd

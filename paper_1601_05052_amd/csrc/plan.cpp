@@ -87,6 +87,7 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
             L->recs.assign((size_t)n_tiles * v.waves * regwin_rows(v, R) * regwin_rd(v), 0);
     }
     int32_t max_spread = 0;
+    int32_t max_reach = 0;  // largest (offset - staged-row start) + 1 over rows and tiles
     int64_t need = 0;  // regwin: largest staged-row index a lane window touches, + 1
     bool ok = true;
     // Row spans: per (accumulator tile, time tile), the rows [lo, hi) with at
@@ -112,8 +113,13 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
                 hi = std::max(hi, o);
             }
             max_spread = std::max(max_spread, hi - lo);
+            // Register-window rows start on a multiple of 4 samples, so the
+            // staging's 16-byte loads are aligned for every input type
+            // (floor, also for the adjoint's negative offsets).
+            const int32_t b = v.kind == KIND_REGWIN ? lo - (((lo % 4) + 4) % 4) : lo;
+            max_reach = std::max(max_reach, hi - b + 1);
             if (build)
-                L->base[(size_t)k * R + r] = lo;
+                L->base[(size_t)k * R + r] = b;
             if (want_span) {
                 row_lo[r] = lo;
                 row_hi[r] = hi;
@@ -130,7 +136,7 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
             for (int32_t w = 0; w < v.waves; ++w) {
                 int32_t wmin = std::numeric_limits<int32_t>::max(), wmax = 0;
                 for (int32_t j = 0; j < TDW; ++j) {
-                    const int32_t o = offset_of(p, direction, r, std::min(A - 1, k * TA + w * TDW + j)) - lo;
+                    const int32_t o = offset_of(p, direction, r, std::min(A - 1, k * TA + w * TDW + j)) - b;
                     wmin = std::min(wmin, o);
                     wmax = std::max(wmax, o);
                 }
@@ -152,7 +158,7 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
                     rec[0] = u_bytes | (nq << 20);
                     for (int32_t j = 0; j < TDW; ++j) {
                         const uint32_t o = (uint32_t)(offset_of(p, direction, r, std::min(A - 1, k * TA + w * TDW + j)) -
-                                                      lo - ws);  // 0 <= o <= nwr - items_t < 256
+                                                      b - ws);  // 0 <= o <= nwr - items_t < 256
                         rec[1 + j / 4] = (int32_t)((uint32_t)rec[1 + j / 4] | (o << (8 * (j % 4))));
                     }
                 }
@@ -210,7 +216,7 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
         L->rows_per_chunk = (int32_t)rpc;
         L->lds_bytes = (int32_t)(rpc * row_bytes);
     } else {
-        const int64_t w64 = (std::max<int64_t>(need, (int64_t)TT + max_spread) + 63) & ~int64_t(63);
+        const int64_t w64 = (std::max<int64_t>(need, (int64_t)TT + max_reach - 1) + 63) & ~int64_t(63);
         if (w64 > (int64_t)64 * v.kmax)
             return;
         const int64_t rows = (int64_t)v.waves * v.rpw;
@@ -305,15 +311,18 @@ int plan_tables(const dd_plan *p, int direction, const Variant &v, const TileTab
     if (!ins.second)
         free_tables(t);  // another thread built it first
     *out = &ins.first->second;
+    p->host_tables.emplace(std::make_pair(direction, (int)v.id), std::move(L));
     return DD_OK;
 }
 
-int make_args(const dd_plan *p, int direction, const Variant &v, const void *in, int64_t in_stride,
-              float *out, int64_t out_stride, SrsArgs *a) {
-    const TileTables *t = nullptr;
-    int rc = plan_tables(p, direction, v, &t);
-    if (rc != DD_OK)
-        return rc;
+const Layout *plan_host_layout(const dd_plan *p, int direction, int32_t variant) {
+    std::lock_guard<std::mutex> lock(p->mu);
+    auto it = p->host_tables.find({direction, (int)variant});
+    return it == p->host_tables.end() ? nullptr : &it->second;
+}
+
+void args_dims(const dd_plan *p, int direction, const void *in, int64_t in_stride, float *out, int64_t out_stride,
+               SrsArgs *a) {
     a->in = in;
     a->in_stride = in_stride;
     a->out = out;
@@ -329,6 +338,15 @@ int make_args(const dd_plan *p, int direction, const Variant &v, const void *in,
         a->n_acc = p->C;
         a->n_rows = p->D;
     }
+}
+
+int make_args(const dd_plan *p, int direction, const Variant &v, const void *in, int64_t in_stride,
+              float *out, int64_t out_stride, SrsArgs *a) {
+    const TileTables *t = nullptr;
+    int rc = plan_tables(p, direction, v, &t);
+    if (rc != DD_OK)
+        return rc;
+    args_dims(p, direction, in, in_stride, out, out_stride, a);
     a->rel = t->d_rel;
     a->base = t->d_base;
     a->recs = t->d_recs;

@@ -31,12 +31,13 @@ static double estimate_seconds(const dd_plan *p, int direction, const Variant &v
     return work / (static_cast<double>(v.rate) * 1e12 * fill) + staged / 8e12;
 }
 
-int32_t best_by_model(const dd_plan *p, int direction, const int32_t *cand, int32_t n_cand) {
+int32_t best_by_model(const dd_plan *p, int direction, int32_t in_type, const int32_t *cand, int32_t n_cand) {
     int32_t best = -1;
     double best_t = 0.0;
+    const int32_t kt = direction == DD_FORWARD ? in_type : (int32_t)DD_F32;
     for (int32_t i = 0; i < n_cand; ++i) {
         const Variant *v = find_variant(cand[i]);
-        if (!v || !variant_fits(p, direction, *v))
+        if (!v || !has_kernel(*v, kt) || !variant_fits(p, direction, *v))
             continue;
         int32_t wcap = 0;
         {
@@ -53,13 +54,12 @@ int32_t best_by_model(const dd_plan *p, int direction, const int32_t *cand, int3
 }
 
 int32_t default_variant(const dd_plan *p, int direction, int32_t in_type) {
-    (void)in_type;
     int32_t n = 0;
     variants(&n);
     std::vector<int32_t> all(n);
     for (int32_t i = 0; i < n; ++i)
         all[i] = i;
-    return best_by_model(p, direction, all.data(), n);
+    return best_by_model(p, direction, in_type, all.data(), n);
 }
 
 int32_t choose_variant(const dd_plan *p, int direction, int32_t in_type) {

@@ -13,9 +13,9 @@
 // moved from local memory into registers.
 //
 // Staging: every wave owns RPW rows of each chunk of NW*RPW input rows.  Its
-// lanes fetch them with bounds-checked buffer loads (samples outside
-// [0, in_valid) read as zero; float32 rows four samples per load) into
-// registers two chunks ahead and write them to the other of two LDS chunk
+// lanes fetch them with bounds-checked buffer loads of four samples each
+// (samples outside [0, in_valid) read as zero) into registers two chunks
+// ahead, widen them to binary32 and write them to the other of two LDS chunk
 // buffers; one barrier per chunk.
 #pragma once
 
@@ -23,13 +23,19 @@
 
 #include <cstdint>
 
+#ifdef DD_STUDY
+#include "study_regwin_asm.h"  // every window shape of the study's grid
+#else
 #include "regwin_asm.h"
+#endif
 #include "srs_tile.h"
 
 namespace dd {
 namespace dev {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v3i __attribute__((ext_vector_type(3)));
+typedef int v2i __attribute__((ext_vector_type(2)));
 
 constexpr uint32_t kBufferFlags = 0x00020000u;  // raw buffer, 32-bit data format (gfx9 V# word 3)
 constexpr uint32_t kOutOfRange = 0x80000000u;   // any offset >= num_records reads 0
@@ -85,79 +91,132 @@ __device__ __forceinline__ uint32_t lds_address(const float *p) {
     return static_cast<uint32_t>(reinterpret_cast<uintptr_t>((const __attribute__((address_space(3))) float *)p));
 }
 
-// Quad-wide staging for float32 rows: lane l fetches samples
-// g0 + 4l + 256k .. +3 (k < KQ) with one 16-byte bounds-checked load each.
-// The buffer range is clipped as in fetch_row; dwords past it read zero.
-template <int KQ>
-__device__ __forceinline__ void fetch_row_q(const float *__restrict__ in, int64_t in_stride, int64_t in_valid,
-                                            int32_t row, int64_t g0, int32_t wcap, int lane, v4f (&pre)[KQ]) {
-    const float *rp = in + static_cast<int64_t>(row) * in_stride;
+// Raw dwords of one staged quad (four consecutive samples) as loaded: float32
+// exactly the quad; float16 and u8 one dword more, so that a quad starting
+// inside a dword can be realigned.
+template <typename TIn>
+struct QuadRaw;
+template <>
+struct QuadRaw<float> {
+    typedef v4i T;
+};
+template <>
+struct QuadRaw<_Float16> {
+    typedef v3i T;
+};
+template <>
+struct QuadRaw<uint8_t> {
+    typedef v2i T;
+};
+
+// Staging loads of one row: lane l fetches quad k (k < KL), samples
+// g0 + 4l + 256k .. +3, with one bounds-checked buffer load.  g0 is a
+// multiple of 4 (register-window rows start there), so a quad lies wholly
+// before sample 0 -- it reads zero (adjoint windows near t = 0) -- or wholly
+// at or after it.  The data is only used when the row is stored to LDS (two
+// chunks later), so the loads' latency stays hidden.
+//   float32: the buffer's range is clipped to min(in_valid, g0 + wcap)
+//     samples; samples past it read zero (the adjoint relies on zeros past
+//     its input).
+//   float16 / u8 (forward only): rows may start at any byte, so the loads are
+//     made from the dword boundary at or below the quad, one dword longer than
+//     the quad; *delta (the quad's byte offset in its first dword, the same for
+//     every quad of the row) realigns them when they are stored.  The range is
+//     clipped to the dword holding the last valid sample: every dword read
+//     holds at least one byte of the caller's buffer, and bytes past the valid
+//     samples only reach samples that no stored output reads.
+template <typename TIn, int KL>
+__device__ __forceinline__ void fetch_quads(const TIn *__restrict__ in, int64_t in_stride, int64_t in_valid,
+                                            int32_t row, int64_t g0, int32_t wcap, int lane,
+                                            typename QuadRaw<TIn>::T (&raw)[KL], uint32_t *delta) {
+    constexpr uint32_t ES = sizeof(TIn);
+    const TIn *rp = in + static_cast<int64_t>(row) * in_stride;
     const int64_t end = min(in_valid, g0 + wcap);
-    const int32_t n_bytes = end > 0 ? static_cast<int32_t>(end * 4) : 0;
-    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(rp), 0, n_bytes, kBufferFlags);
-    const uint32_t voff = static_cast<uint32_t>(g0 + 4 * lane) * 4u;  // g0 >= 0, < 2^29
+    const int64_t q0 = g0 + 4 * lane;  // first sample of quad 0 (multiple of 4)
+    if constexpr (ES == 4) {
+        const int32_t end_b = end > 0 ? static_cast<int32_t>(end * 4) : 0;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(const_cast<TIn *>(rp), 0, end_b, kBufferFlags);
 #pragma unroll
-    for (int k = 0; k < KQ; ++k)
-        pre[k] = __builtin_bit_cast(v4f, __builtin_amdgcn_raw_buffer_load_b128(rs, voff + k * 1024u, 0, 0));
+        for (int k = 0; k < KL; ++k) {
+            const int64_t s = q0 + 256 * k;  // |s| < 2^29
+            const uint32_t off = s >= 0 ? static_cast<uint32_t>(s) * 4u : kOutOfRange;
+            raw[k] = __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0));
+        }
+        *delta = 0;
+    } else {
+        const uintptr_t ra = reinterpret_cast<uintptr_t>(rp);
+        const uint32_t a_r = static_cast<uint32_t>(ra & 3u);  // row start within its dword
+        const uint32_t end_b = end > 0 ? static_cast<uint32_t>(end) * ES + a_r : 0;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            reinterpret_cast<void *>(ra - a_r), 0, static_cast<int32_t>((end_b + 3u) & ~3u), kBufferFlags);
+        // Every quad starts at the same byte within a dword (4 * ES bytes apart).
+        const uint32_t dl = (static_cast<uint32_t>(g0) * ES + a_r) & 3u;  // wave-uniform
+#pragma unroll
+        for (int k = 0; k < KL; ++k) {
+            const int64_t s = q0 + 256 * k;
+            const uint32_t off = s >= 0 ? static_cast<uint32_t>(s) * ES + a_r - dl : kOutOfRange;
+            if constexpr (ES == 1)
+                raw[k] = __builtin_bit_cast(v2i, __builtin_amdgcn_raw_buffer_load_b64(rs, off, 0, 0));
+            else
+                raw[k] = __builtin_bit_cast(v3i, __builtin_amdgcn_raw_buffer_load_b96(rs, off, 0, 0));
+        }
+        *delta = dl;
+    }
+}
+
+// One staged quad, realigned by delta bytes (float16 / u8) and widened to
+// binary32.  alignbyte(hi, lo, d) is bytes d .. d + 3 of hi:lo.
+__device__ __forceinline__ v4f widen_quad(const v4i &r, uint32_t) { return __builtin_bit_cast(v4f, r); }
+__device__ __forceinline__ v4f widen_quad(const v3i &r, uint32_t delta) {
+    const uint32_t lo = __builtin_amdgcn_alignbyte(static_cast<uint32_t>(r.y), static_cast<uint32_t>(r.x), delta);
+    const uint32_t hi = __builtin_amdgcn_alignbyte(static_cast<uint32_t>(r.z), static_cast<uint32_t>(r.y), delta);
+    return v4f{static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(lo & 0xffffu))),
+               static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(lo >> 16))),
+               static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(hi & 0xffffu))),
+               static_cast<float>(__builtin_bit_cast(_Float16, static_cast<uint16_t>(hi >> 16)))};
+}
+__device__ __forceinline__ v4f widen_quad(const v2i &r, uint32_t delta) {
+    const uint32_t w = __builtin_amdgcn_alignbyte(static_cast<uint32_t>(r.y), static_cast<uint32_t>(r.x), delta);
+    return v4f{static_cast<float>(w & 0xffu), static_cast<float>((w >> 8) & 0xffu),
+               static_cast<float>((w >> 16) & 0xffu), static_cast<float>(w >> 24)};
 }
 
 // Staging of input rows into padded LDS rows for the register-window forms.
 // Every wave owns RPW rows of each chunk of NW*RPW rows; fetch() loads them
-// into registers (float32 rows four samples per load, narrower types per
-// sample), store() writes them into a chunk buffer.  Padded layout: logical
-// quad Q at physical quad Q + floor(Q/S) (no padding when S == 1).
+// into registers a quad (four samples) per lane and load, store() widens
+// them to binary32 and writes each quad with one 16-byte LDS write.  Padded
+// layout: logical quad Q at physical quad Q + floor(Q/S) (no padding when
+// S == 1).
 template <typename TIn, int S, int NW, int RPW, int KMAX>
 struct ChunkStager {
-    static constexpr bool WIDE = sizeof(TIn) == 4;
-    static constexpr int KQ = (KMAX + 3) / 4;  // 256-sample quad pieces
+    static constexpr int KL = (KMAX + 3) / 4;  // quads per lane per row (256 samples each over the wave)
     static constexpr int CR = NW * RPW;
-    static constexpr int32_t piece_dw = S == 1 ? 64 : 64 / S * (S + 1);  // physical dwords per 64 samples
-    static constexpr int32_t qpiece_dw = 4 * piece_dw;                   // physical dwords per 256 samples
+    typedef typename QuadRaw<TIn>::T Raw;
     const TIn *in;
     ctab *base_tile;
     const SrsDims &d;
     int64_t t0;
-    int wave, lane, nk;
-    int32_t row_dw, lane_st, lane_stq;
-    float pre[RPW][WIDE ? 1 : KMAX];
-    v4f preq[RPW][WIDE ? KQ : 1];
-    int wide_ok[RPW];  // 1: the row was fetched with quad loads (wave-uniform)
+    int wave, lane;
+    int32_t row_dw;
+    Raw raw[RPW][KL];
+    uint32_t delta[RPW];  // realignment of each fetched row (wave-uniform)
 
     __device__ ChunkStager(const TIn *in_, ctab *base_tile_, const SrsDims &d_, int64_t t0_, int wave_, int lane_)
         : in(in_), base_tile(base_tile_), d(d_), t0(t0_), wave(wave_), lane(lane_) {
-        nk = d.wcap >> 6;  // wcap is a multiple of 64
         row_dw = S == 1 ? d.wcap : d.wcap / S * (S + 1);
-        lane_st = S == 1 ? lane : 4 * ((lane >> 2) + ((lane >> 2) / S)) + (lane & 3);
-        lane_stq = S == 1 ? 4 * lane : 4 * (lane + lane / S);
     }
+
+    // Physical dword offset of logical quad Q in a padded row.
+    __device__ static __forceinline__ int32_t quad_dw(int32_t Q) { return 4 * (S == 1 ? Q : Q + Q / S); }
 
     __device__ __forceinline__ void fetch(int32_t c) {
 #pragma unroll
         for (int q = 0; q < RPW; ++q) {
             const int32_t row = c * CR + wave * RPW + q;
-            if (row < d.n_rows) {
-                const int64_t g0 = t0 + base_tile[row];
-                if constexpr (WIDE) {
-                    wide_ok[q] = __builtin_amdgcn_readfirstlane(g0 >= 0 ? 1 : 0);
-                    if (g0 >= 0) {
-                        fetch_row_q<KQ>(reinterpret_cast<const float *>(in), d.in_stride, d.in_valid, row, g0, d.wcap,
-                                        lane, preq[q]);
-                    } else {
-                        // Window starts before sample 0 (adjoint near t = 0):
-                        // per-sample loads; preq[q][k][i] holds sample
-                        // g0 + lane + 64(4k + i).
-                        float tmp[KMAX];
-                        fetch_row<TIn, KMAX>(in, d.in_stride, d.in_valid, row, g0, nk, lane, tmp);
-#pragma unroll
-                        for (int k = 0; k < KQ; ++k)
-#pragma unroll
-                            for (int i = 0; i < 4; ++i)
-                                preq[q][k][i] = 4 * k + i < KMAX ? tmp[min(4 * k + i, KMAX - 1)] : 0.f;
-                    }
-                } else {
-                    fetch_row<TIn, KMAX>(in, d.in_stride, d.in_valid, row, g0, nk, lane, pre[q]);
-                }
-            }
+            if (row < d.n_rows)
+                fetch_quads<TIn, KL>(in, d.in_stride, d.in_valid, row, t0 + base_tile[row], d.wcap, lane, raw[q],
+                                     &delta[q]);
         }
     }
 
@@ -168,25 +227,11 @@ struct ChunkStager {
             const int32_t rr = wave * RPW + q;
             if (c * CR + rr < d.n_rows) {
                 float *rowp = buf + rr * row_dw;
-                if constexpr (WIDE) {
-                    if (wide_ok[q]) {
 #pragma unroll
-                        for (int k = 0; k < KQ; ++k)
-                            if (4 * lane + 256 * k < d.wcap)
-                                *reinterpret_cast<v4f *>(rowp + lane_stq + qpiece_dw * k) = preq[q][k];
-                    } else {
-#pragma unroll
-                        for (int k = 0; k < KQ; ++k)
-#pragma unroll
-                            for (int i = 0; i < 4; ++i)
-                                if (4 * k + i < nk)
-                                    rowp[lane_st + piece_dw * (4 * k + i)] = preq[q][k][i];
-                    }
-                } else {
-#pragma unroll
-                    for (int k = 0; k < KMAX; ++k)
-                        if (k < nk)
-                            rowp[lane_st + piece_dw * k] = pre[q][k];
+                for (int k = 0; k < KL; ++k) {
+                    const int32_t Q = 64 * k + lane;  // logical quad
+                    if (4 * Q < d.wcap)
+                        *reinterpret_cast<v4f *>(rowp + quad_dw(Q)) = widen_quad(raw[q][k], delta[q]);
                 }
             }
         }

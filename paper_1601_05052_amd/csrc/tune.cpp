@@ -123,7 +123,7 @@ int tune_candidates(const dd_plan *p, int direction, int32_t in_type, int32_t re
         const int32_t in_t = direction == DD_FORWARD ? in_type : (int32_t)DD_F32;
         for (int32_t i = 0; i < n_cand && rc == DD_OK; ++i) {
             const Variant *v = find_variant(cand[i]);
-            if (!v || !variant_fits(p, direction, *v))
+            if (!v || !has_kernel(*v, in_t) || !variant_fits(p, direction, *v))
                 continue;
             rc = run_direction(p, direction, in_t, *v, d_in, in_cols, d_out, out_cols, stream);  // warm-up
             if (rc != DD_OK)

@@ -2,14 +2,54 @@
 // launches to the per-input-type instantiation units.
 #include <hip/hip_runtime.h>
 
+#include <vector>
+
 #include "internal.h"
 #include "srs_dims.h"
+#ifdef DD_STUDY
+#include "study_variants.def"
+#else
 #include "srs_variants.def"
+#endif
 
 namespace dd {
 
+#ifdef DD_STUDY
+// Study library: float32 single-beam kernels only, compiled in slices.
+static_assert(DD_STUDY_N_SLICES == 8, "eight study slices");
+extern const StudyEntry *study_slice_0, *study_slice_1, *study_slice_2, *study_slice_3, *study_slice_4,
+    *study_slice_5, *study_slice_6, *study_slice_7;
+extern const int32_t study_slice_n_0, study_slice_n_1, study_slice_n_2, study_slice_n_3, study_slice_n_4,
+    study_slice_n_5, study_slice_n_6, study_slice_n_7;
+static const LaunchFn *study_launchers() {
+    static const std::vector<LaunchFn> table = [] {
+        const StudyEntry *s[] = {study_slice_0, study_slice_1, study_slice_2, study_slice_3,
+                                 study_slice_4, study_slice_5, study_slice_6, study_slice_7};
+        const int32_t n[] = {study_slice_n_0, study_slice_n_1, study_slice_n_2, study_slice_n_3,
+                             study_slice_n_4, study_slice_n_5, study_slice_n_6, study_slice_n_7};
+        std::vector<LaunchFn> t;
+        for (int k = 0; k < 8; ++k)
+            for (int32_t i = 0; i < n[k]; ++i) {
+                if (static_cast<size_t>(s[k][i].id) >= t.size())
+                    t.resize(s[k][i].id + 1, nullptr);
+                t[s[k][i].id] = s[k][i].fn;
+            }
+        return t;
+    }();
+    return table.data();
+}
+static const LaunchFn *launchers_of(int32_t in_type) { return in_type == DD_F32 ? study_launchers() : nullptr; }
+static const void *const *multis_of(int32_t) { return nullptr; }
+#else
 extern const LaunchFn *launchers_f32, *launchers_f16, *launchers_u8;
 extern const void *const *multis_f32, *const *multis_f16, *const *multis_u8;
+static const LaunchFn *launchers_of(int32_t in_type) {
+    return in_type == DD_F32 ? launchers_f32 : in_type == DD_F16 ? launchers_f16 : launchers_u8;
+}
+static const void *const *multis_of(int32_t in_type) {
+    return in_type == DD_F32 ? multis_f32 : in_type == DD_F16 ? multis_f16 : multis_u8;
+}
+#endif
 
 namespace {
 
@@ -56,8 +96,13 @@ int32_t max_lds_bytes() {
 }
 
 const void *multi_kernel(const Variant &v, int32_t in_type) {
-    const void *const *t = in_type == DD_F32 ? multis_f32 : in_type == DD_F16 ? multis_f16 : multis_u8;
-    return t[v.id];
+    const void *const *t = multis_of(in_type);
+    return t ? t[v.id] : nullptr;
+}
+
+bool has_kernel(const Variant &v, int32_t in_type) {
+    const LaunchFn *t = launchers_of(in_type);
+    return t && t[v.id];
 }
 
 hipError_t launch_srs(const Variant &v, int32_t in_type, const SrsArgs &a, hipStream_t stream) {
@@ -77,7 +122,9 @@ hipError_t launch_srs(const Variant &v, int32_t in_type, const SrsArgs &a, hipSt
         return hipSuccess;
     if (blocks > 0x7fffffffull)
         return hipErrorInvalidConfiguration;
-    const LaunchFn *t = in_type == DD_F32 ? launchers_f32 : in_type == DD_F16 ? launchers_f16 : launchers_u8;
+    const LaunchFn *t = launchers_of(in_type);
+    if (!t || !t[v.id])
+        return hipErrorInvalidDeviceFunction;  // callers check has_kernel first
     return t[v.id](a, d, static_cast<uint32_t>(blocks), static_cast<size_t>(a.lds_bytes), stream);
 }
 

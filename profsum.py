@@ -16,7 +16,14 @@
         device-to-device copy of N bytes (default 256 MiB) in the same run,
         whose kernel name contains "copyBuffer".
 
-Reads only the CSV files; prints Markdown on stdout.
+    python3 profsum.py study JSON [--curated N]
+        The auto-tuning study (bench.py --tune-study): per instance the
+        optimum, mean and spread over the variants that fit, the optimum's
+        signal-to-noise ratio and Chebyshev bound, the best fixed variant, the
+        best of the first N (curated) variants against the optimum, the kind
+        and tile of each optimum, and rate histograms.
+
+Reads only the CSV / JSON files; prints Markdown on stdout.
 """
 from __future__ import annotations
 
@@ -134,6 +141,68 @@ def counters(fetch_dir, write_dir, kernel, copy_bytes):
             print("`%s`: %.4g bytes per dispatch from HBM-side counters." % (n, b))
 
 
+KINDS = {0: "LDS", 1: "register window", 2: "direct"}
+
+
+def study(path, curated):
+    import json
+    with open(path) as f:
+        d = json.load(f)
+    var = {v[0]: v for v in d["variants"]}
+    rows = d["instances"]
+
+    def desc(vid):
+        _, it, acc, waves, kind = var[vid]
+        return "%s %dx%d, %d waves (%d samples x %d rows)" % (KINDS[kind], it, acc, waves, 64 * it, acc * waves)
+
+    print("Library: `%s`, %d tile variants (ids below %d: the product library's curated list)."
+          % (d.get("library"), len(var), curated))
+    print()
+    print("| setup | DMs | variants | optimum | GFLOP/s | mean | std | SNR | Chebyshev | fixed | tuned / fixed "
+          "| best curated | optimum / best curated | real time |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|---|---|---|")
+    for r in rows:
+        g = {int(k): v for k, v in r["gflops"].items()}
+        cur = {k: v for k, v in g.items() if k < curated}
+        bc = max(cur, key=cur.get) if cur else None
+        print("| %s | %d | %d | %d | %.0f | %.0f | %.0f | %.2f | %.2f | %d | %.2f | %s | %s | %s |" % (
+            r["setup"], r["n_dm"], r["n_variants"], r["best"], r["best_gflops"], r["mean_gflops"], r["std_gflops"],
+            r["snr"], r["chebyshev_bound"], r["fixed_variant"], r["tuned_over_fixed"],
+            "-" if bc is None else "%d" % bc, "-" if bc is None else "%.2f" % (r["best_gflops"] / cur[bc]),
+            "yes" if r["realtime"] else "no"))
+    print()
+    print("Optima and fixed variants:")
+    print()
+    for vid in sorted({r["best"] for r in rows} | {r["fixed_variant"] for r in rows}):
+        print("* %d: %s" % (vid, desc(vid)))
+    for setup in sorted({r["setup"] for r in rows}):
+        sel = [r for r in rows if r["setup"] == setup]
+        r = max(sel, key=lambda x: x["n_dm"] if x["n_dm"] <= 2048 else -1)
+        vals = sorted(r["gflops"].values())
+        lo, hi = 0.0, max(vals)
+        nb = 12
+        w = (hi - lo) / nb
+        print()
+        print("Rate histogram, %s, %d DMs (%d variants):" % (setup, r["n_dm"], len(vals)))
+        print()
+        print("| GFLOP/s | variants |")
+        print("|---|---|")
+        for b in range(nb):
+            a0, a1 = lo + b * w, lo + (b + 1) * w
+            n = sum(1 for v in vals if a0 <= v < a1 or (b == nb - 1 and v == hi))
+            print("| %.0f-%.0f | %s |" % (a0, a1, "#" * n if n else "0"))
+        # best per kind at this instance
+        print()
+        print("Best per kind at %d DMs:" % r["n_dm"])
+        print()
+        for kind in sorted(KINDS):
+            ks = {int(k): v for k, v in r["gflops"].items() if var[int(k)][4] == kind}
+            if ks:
+                b = max(ks, key=ks.get)
+                print("* %s: variant %d, %.0f GFLOP/s (%s); %d variants of this kind fit"
+                      % (KINDS[kind], b, ks[b], desc(b), len(ks)))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -146,9 +215,14 @@ def main(argv=None):
     c.add_argument("write_dir")
     c.add_argument("kernel")
     c.add_argument("--copy-bytes", type=int, default=256 << 20)
+    st = sub.add_parser("study")
+    st.add_argument("json")
+    st.add_argument("--curated", type=int, default=46)
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         trace(a.dir, a.kernel, a.calls_after)
+    elif a.cmd == "study":
+        study(a.json, a.curated)
     else:
         counters(a.fetch_dir, a.write_dir, a.kernel, a.copy_bytes)
 

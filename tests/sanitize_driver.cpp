@@ -18,9 +18,19 @@
 #include "internal.h"
 
 // The per-input-type kernel tables live in the HIP units, which this build
-// leaves out; nothing here launches a kernel.
+// leaves out: every entry is a stand-in that launches nothing (no call here
+// gets as far as a launch: the device is missing).
 namespace dd {
-const LaunchFn *launchers_f32 = nullptr, *launchers_f16 = nullptr, *launchers_u8 = nullptr;
+static hipError_t no_launch(const SrsArgs &, const dev::SrsDims &, uint32_t, size_t, hipStream_t) {
+    return hipErrorInvalidDeviceFunction;
+}
+static const LaunchFn *stand_in_table() {
+    static LaunchFn t[1024];
+    for (LaunchFn &f : t)
+        f = no_launch;
+    return t;
+}
+const LaunchFn *launchers_f32 = stand_in_table(), *launchers_f16 = launchers_f32, *launchers_u8 = launchers_f32;
 const void *const *multis_f32 = nullptr, *const *multis_f16 = nullptr, *const *multis_u8 = nullptr;
 }  // namespace dd
 

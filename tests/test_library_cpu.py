@@ -259,3 +259,4 @@ def test_output_checks_reject_bad_outs_on_the_host():
         _check_output(torch.empty((3, 10)), p, torch.device("meta"))
     with pytest.raises(TypeError):
         _check_output(np.zeros((3, 10), np.float32), p, cpu)
+

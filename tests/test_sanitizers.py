@@ -14,7 +14,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_1601_05052_amd", "csrc")
-HOST_SOURCES = ["plan.cpp", "select.cpp", "api.cpp", "variants.cpp"]
+HOST_SOURCES = ["plan.cpp", "select.cpp", "api.cpp", "variants.cpp"]  # noalloc.hip needs device code
 SAN = ["-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-g", "-O1"]
 
 
