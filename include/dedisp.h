@@ -120,6 +120,25 @@ int dd_plan_prepare(dd_plan *plan, dd_direction direction, dd_dtype in_type);
 int dd_dedisperse(const dd_plan *plan, const void *d_in, dd_dtype in_type, int64_t in_stride,
                   float *d_out, int64_t out_stride, void *stream);
 
+/* Allocation-free dd_dedisperse, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, result and checks as dd_dedisperse, and
+ * the same kernels; the plan's tile tables come from the plan's host copy
+ * and are staged, by asynchronous copies on `stream`, into one fixed device
+ * array of the library (16 MiB, held by each device the library runs on until
+ * the process ends), not into memory the plan allocates.  It calls no
+ * hipMalloc, hipFree or other allocating routine.
+ *   - The plan's forward tables for (in_type's tile variant) must exist: call
+ *     dd_plan_prepare(plan, DD_FORWARD, in_type) (or dd_dedisperse once)
+ *     beforehand, where allocation is allowed; otherwise DD_EINVAL.
+ *   - DD_EUNSUPPORTED if the tables need more than 16 MiB (e.g. a plan of
+ *     more than about four million delay-table entries on an LDS-form tile).
+ *   - Every call on one device shares the array and overwrites it: calls that
+ *     overlap on a device (several host threads, or streams with no ordering
+ *     between them) race and must be serialised by the caller. */
+int dd_dedisperse_noalloc(const dd_plan *plan, const void *d_in, dd_dtype in_type, int64_t in_stride,
+                          float *d_out, int64_t out_stride, void *stream);
+
 /* Adjoint (transpose) of dd_dedisperse for binary32 data:
  *   d_grad_in[ch*in_stride + tau] = sum over i with 0 <= tau - delay[i][ch] < n_samples
  *                                   of d_grad_out[i*out_stride + tau - delay[i][ch]]

@@ -23,8 +23,8 @@ import numpy as np
 from . import _lib
 from ._lib import DD_ADJOINT, DD_F16, DD_F32, DD_FORWARD, DD_U8, DedispError, check  # noqa: F401
 
-__all__ = ["Plan", "Batch", "Realtime", "search_boxcar", "Dedisperse", "dedisperse", "dedisperse_adjoint",
-           "DedispError",
+__all__ = ["Plan", "Batch", "Realtime", "search_boxcar", "Dedisperse", "dedisperse", "dedisperse_noalloc",
+           "dedisperse_adjoint", "DedispError",
            "tile_variants", "DD_F32", "DD_F16", "DD_U8", "DD_FORWARD", "DD_ADJOINT"]
 
 
@@ -164,6 +164,20 @@ def dedisperse(x, plan: Plan, out=None):
         check(_lib.lib().dd_dedisperse(plan.handle, ctypes.c_void_p(x.data_ptr()), _dtype_code(x.dtype),
                                        x.stride(0), ctypes.c_void_p(out.data_ptr()), out.stride(0),
                                        _stream_handle(x.device)))
+    return out
+
+
+def dedisperse_noalloc(x, plan: Plan, out):
+    """``dedisperse`` through the allocation-free entry (dd_dedisperse_noalloc):
+    ``out`` is required; the plan's forward tables must have been built
+    (``plan.prepare(DD_FORWARD, dtype)`` or one ``dedisperse`` call)."""
+    _check_input(x, plan)
+    _check_output(out, plan, x.device)
+    torch = _torch()
+    with torch.cuda.device(x.device):
+        check(_lib.lib().dd_dedisperse_noalloc(plan.handle, ctypes.c_void_p(x.data_ptr()), _dtype_code(x.dtype),
+                                               x.stride(0), ctypes.c_void_p(out.data_ptr()), out.stride(0),
+                                               _stream_handle(x.device)))
     return out
 
 

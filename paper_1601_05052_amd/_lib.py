@@ -36,6 +36,7 @@ SIGNATURES = {
     "dd_plan_delay_table": [vp, vp],
     "dd_plan_prepare": [vp, ctypes.c_int, ctypes.c_int],
     "dd_dedisperse": [vp, vp, ctypes.c_int, i64, vp, i64, vp],
+    "dd_dedisperse_noalloc": [vp, vp, ctypes.c_int, i64, vp, i64, vp],
     "dd_dedisperse_adjoint": [vp, vp, i64, vp, i64, vp],
     "dd_tile_count": [P(i32)],
     "dd_tile_info": [i32, P(i32), P(i32), P(i32), P(i32)],

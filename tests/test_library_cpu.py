@@ -260,3 +260,20 @@ def test_output_checks_reject_bad_outs_on_the_host():
     with pytest.raises(TypeError):
         _check_output(np.zeros((3, 10), np.float32), p, cpu)
 
+
+def test_noalloc_entry_refuses_unprepared_plan_before_gpu_work():
+    """dd_dedisperse_noalloc stages the plan's host tables; a plan whose tables
+    were never built is refused (DD_EINVAL) before any GPU call, as are the
+    forward's argument errors."""
+    L = _lib.lib()
+    p = Plan(4, 1400.0, 1.0, 1e-4, 0.0, 1.0, 3, 10)
+    T = p.input_samples
+    buf_in = ctypes.create_string_buffer(4 * 4 * T)
+    buf_out = ctypes.create_string_buffer(4 * 3 * 10)
+    rc = L.dd_dedisperse_noalloc(p.handle, ctypes.addressof(buf_in), 0, T, ctypes.addressof(buf_out), 10, None)
+    assert rc == _lib.DD_EINVAL
+    assert b"dd_plan_prepare" in L.dd_last_error()
+    assert L.dd_dedisperse_noalloc(p.handle, ctypes.addressof(buf_in), 0, T - 1, ctypes.addressof(buf_out), 10,
+                                   None) == _lib.DD_ESHAPE
+    assert L.dd_dedisperse_noalloc(None, ctypes.addressof(buf_in), 0, T, ctypes.addressof(buf_out), 10,
+                                   None) == _lib.DD_EINVAL
