@@ -420,9 +420,9 @@ def tune_study(torch, dd, stream, reps=5):
             for vid in variants:
                 try:
                     plan.set_tile(vid)
+                    ms, _ = timed(torch, lambda: dd.dedisperse(x, plan, out=out), reps, 2, stream)
                 except dd.DedispError:
                     continue   # the tile's window does not fit this instance
-                ms, _ = timed(torch, lambda: dd.dedisperse(x, plan, out=out), reps, 2, stream)
                 gf[vid] = st.adds / (ms * 1e-3) / 1e9
             plan.set_tile(-1)
             model = plan.get_tile()

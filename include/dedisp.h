@@ -168,12 +168,40 @@ int dd_tile_info(int32_t variant, int32_t *items_t, int32_t *items_acc, int32_t 
 
 /* Force a tile variant for (direction, in_type) on this plan, or -1 to
  * return to the automatic choice.  DD_EUNSUPPORTED if the variant cannot
- * serve this plan (its staging window would not fit in LDS). */
+ * serve this plan (its staging window would not fit in LDS).  The adjoint
+ * works on float32 rows: with DD_ADJOINT, in_type must be DD_F32 (DD_EINVAL
+ * otherwise), here and in dd_plan_set_blocks and dd_autotune. */
 int dd_plan_set_tile(dd_plan *plan, dd_direction direction, dd_dtype in_type, int32_t variant);
 
-/* Tile variant the next call would use. */
+/* Tile variant the next call would use (with a row split, see below, the
+ * variant of its largest block). */
 int dd_plan_get_tile(const dd_plan *plan, dd_direction direction, dd_dtype in_type,
                      int32_t *variant);
+
+/* Row splits.  Every output is a sum over input rows (channels forward, trial
+ * DMs adjoint; Sec. III-A, Algorithm 1).  A plan may split those rows into
+ * consecutive blocks, each summed by its own tile variant in its own launch,
+ * every block after the first continuing the partial sums the previous one
+ * left in the output.  Each output still receives its rows in ascending
+ * order, so the results equal those of one variant for all rows, bit for bit.
+ * Rows whose delay spread across a tile is small can then use a tile that
+ * only fits them (e.g. the adjoint's low trial DMs), the rest a wider one.
+ *   row_starts  n_blocks increasing row indices, the first 0; block b holds
+ *               rows [row_starts[b], row_starts[b+1]) (the last: to the end);
+ *               each start a multiple of its variant's rows per staged chunk
+ *   variants    n_blocks tile variants of the LDS or register-window kinds
+ * dd_plan_set_blocks forces a split for (direction, in_type) (a later
+ * dd_plan_set_tile replaces it); dd_autotune may choose one (Sec. IV-A: the
+ * split is timed against the best single variant).  Batches always use one
+ * variant per beam.  dd_plan_get_blocks reports the launches the next call
+ * makes (one block when there is no split); arrays hold up to DD_MAX_BLOCKS.
+ *   DD_EINVAL  bad counts, starts or ids;  DD_EUNSUPPORTED  a variant cannot
+ *              serve its block */
+#define DD_MAX_BLOCKS 16
+int dd_plan_set_blocks(dd_plan *plan, dd_direction direction, dd_dtype in_type, int32_t n_blocks,
+                       const int32_t *row_starts, const int32_t *variants);
+int dd_plan_get_blocks(const dd_plan *plan, dd_direction direction, dd_dtype in_type, int32_t *n_blocks,
+                       int32_t *row_starts, int32_t *variants);
 
 /* Auto-tuning, Sec. IV-A: time every tile variant that can serve this plan
  * on the current device (mean of `reps` runs after one warm-up, on private

@@ -109,6 +109,23 @@ class Plan:
         check(_lib.lib().dd_plan_get_tile(self._h, direction, dtype, ctypes.byref(v)))
         return v.value
 
+    def set_blocks(self, row_starts, variants, direction: int = DD_FORWARD, dtype: int = DD_F32) -> None:
+        """Split the input rows into blocks (see dd_plan_set_blocks)."""
+        n = len(row_starts)
+        if len(variants) != n:
+            raise ValueError("one variant per block")
+        rs = (ctypes.c_int32 * n)(*[int(r) for r in row_starts])
+        vs = (ctypes.c_int32 * n)(*[int(v) for v in variants])
+        check(_lib.lib().dd_plan_set_blocks(self._h, direction, dtype, n, rs, vs))
+
+    def get_blocks(self, direction: int = DD_FORWARD, dtype: int = DD_F32):
+        """[(first row, variant)] of the launches the next call makes."""
+        n = ctypes.c_int32()
+        rs = (ctypes.c_int32 * _lib.DD_MAX_BLOCKS)()
+        vs = (ctypes.c_int32 * _lib.DD_MAX_BLOCKS)()
+        check(_lib.lib().dd_plan_get_blocks(self._h, direction, dtype, ctypes.byref(n), rs, vs))
+        return [(rs[b], vs[b]) for b in range(n.value)]
+
     def autotune(self, direction: int = DD_FORWARD, dtype: int = DD_F32, reps: int = 3,
                  cache_path: Optional[str] = None, device=None):
         v, ms = ctypes.c_int32(), ctypes.c_float()

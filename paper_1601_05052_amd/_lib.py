@@ -8,6 +8,7 @@ from .build import library_path
 
 DD_OK, DD_EINVAL, DD_ESHAPE, DD_ENOMEM, DD_EHIP, DD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 DD_F32, DD_F16, DD_U8 = 0, 1, 2
+DD_MAX_BLOCKS = 16
 DD_FORWARD, DD_ADJOINT = 0, 1
 
 STATUS_NAMES = {0: "DD_OK", -1: "DD_EINVAL", -2: "DD_ESHAPE", -3: "DD_ENOMEM", -4: "DD_EHIP",
@@ -42,6 +43,8 @@ SIGNATURES = {
     "dd_tile_info": [i32, P(i32), P(i32), P(i32), P(i32)],
     "dd_plan_set_tile": [vp, ctypes.c_int, ctypes.c_int, i32],
     "dd_plan_get_tile": [vp, ctypes.c_int, ctypes.c_int, P(i32)],
+    "dd_plan_set_blocks": [vp, ctypes.c_int, ctypes.c_int, i32, P(i32), P(i32)],
+    "dd_plan_get_blocks": [vp, ctypes.c_int, ctypes.c_int, P(i32), P(i32), P(i32)],
     "dd_autotune": [vp, ctypes.c_int, ctypes.c_int, i32, ctypes.c_char_p, vp, P(i32), P(f32)],
     "dd_batch_create": [P(vp), P(vp), i32, ctypes.c_int],
     "dd_batch_autotune": [P(vp), i32, ctypes.c_int, i32, ctypes.c_char_p, vp],

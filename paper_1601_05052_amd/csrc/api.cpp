@@ -2,6 +2,7 @@
 // selection.  Every check runs before any GPU work is enqueued.
 #include <cstdint>
 #include <cstring>
+#include <vector>
 
 #include "internal.h"
 
@@ -14,6 +15,13 @@ size_t elem_size(int32_t t) { return t == DD_F32 ? 4 : t == DD_F16 ? 2 : 1; }
 bool overlaps(const void *a, size_t na, const void *b, size_t nb) {
     const uintptr_t a0 = reinterpret_cast<uintptr_t>(a), b0 = reinterpret_cast<uintptr_t>(b);
     return a0 < b0 + nb && b0 < a0 + na;
+}
+
+int resolve_blocks(const dd_plan *p, int direction, int32_t in_type, std::vector<Block> *out) {
+    *out = launch_list(p, direction, in_type);
+    if (out->empty())
+        return fail(DD_EUNSUPPORTED, "no tile variant can serve this plan");
+    return DD_OK;
 }
 
 int resolve_variant(const dd_plan *p, int direction, int32_t in_type, const Variant **out) {
@@ -40,6 +48,25 @@ int run_direction(const dd_plan *p, int direction, int32_t in_type, const Varian
     hipError_t e = launch_srs(v, direction == DD_FORWARD ? in_type : (int32_t)DD_F32, a, stream);
     if (e != hipSuccess)
         return fail(DD_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+    return DD_OK;
+}
+
+int run_blocks(const dd_plan *p, int direction, int32_t in_type, const std::vector<Block> &blocks, const void *in,
+               int64_t in_stride, float *out, int64_t out_stride, hipStream_t stream) {
+    const int32_t kt = direction == DD_FORWARD ? in_type : (int32_t)DD_F32;
+    for (const Block &b : blocks) {
+        const Variant *v = find_variant(b.variant);
+        if (!v || !has_kernel(*v, kt))
+            return fail(DD_EUNSUPPORTED, "this library has no kernel of tile variant %d for this input type",
+                        b.variant);
+        SrsArgs a;
+        int rc = make_args(p, direction, *v, in, in_stride, out, out_stride, &a, b.r0, b.r1);
+        if (rc != DD_OK)
+            return rc;
+        hipError_t e = launch_srs(*v, kt, a, stream);
+        if (e != hipSuccess)
+            return fail(DD_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+    }
     return DD_OK;
 }
 
@@ -77,12 +104,12 @@ int dd_dedisperse(const dd_plan *p, const void *d_in, dd_dtype in_type, int64_t 
     int rc = check_forward_args(p, d_in, in_type, in_stride, d_out, out_stride);
     if (rc != DD_OK)
         return rc;
-    const Variant *v = nullptr;
-    rc = resolve_variant(p, DD_FORWARD, in_type, &v);
+    std::vector<Block> blocks;
+    rc = resolve_blocks(p, DD_FORWARD, in_type, &blocks);
     if (rc != DD_OK)
         return rc;
-    return run_direction(p, DD_FORWARD, in_type, *v, d_in, in_stride, d_out, out_stride,
-                         static_cast<hipStream_t>(stream));
+    return run_blocks(p, DD_FORWARD, in_type, blocks, d_in, in_stride, d_out, out_stride,
+                      static_cast<hipStream_t>(stream));
 }
 
 int dd_dedisperse_adjoint(const dd_plan *p, const float *d_grad_out, int64_t out_stride, float *d_grad_in,
@@ -102,14 +129,14 @@ int dd_dedisperse_adjoint(const dd_plan *p, const float *d_grad_out, int64_t out
     const size_t gi_bytes = (static_cast<size_t>(p->C - 1) * in_stride + p->T_in) * 4;
     if (overlaps(d_grad_out, go_bytes, d_grad_in, gi_bytes))
         return fail(DD_ESHAPE, "gradient buffers overlap");
-    const Variant *v = nullptr;
-    int rc = resolve_variant(p, DD_ADJOINT, DD_F32, &v);
+    std::vector<Block> blocks;
+    int rc = resolve_blocks(p, DD_ADJOINT, DD_F32, &blocks);
     if (rc != DD_OK)
         return rc;
     // The adjoint reads rows of grad_out (stride out_stride) and writes rows
     // of grad_in (stride in_stride).
-    return run_direction(p, DD_ADJOINT, DD_F32, *v, d_grad_out, out_stride, d_grad_in, in_stride,
-                         static_cast<hipStream_t>(stream));
+    return run_blocks(p, DD_ADJOINT, DD_F32, blocks, d_grad_out, out_stride, d_grad_in, in_stride,
+                      static_cast<hipStream_t>(stream));
 }
 
 int dd_plan_prepare(dd_plan *p, dd_direction direction, dd_dtype in_type) {
@@ -120,12 +147,17 @@ int dd_plan_prepare(dd_plan *p, dd_direction direction, dd_dtype in_type) {
         return fail(DD_EINVAL, "unknown direction %d", (int)direction);
     if (in_type != DD_F32 && in_type != DD_F16 && in_type != DD_U8)
         return fail(DD_EINVAL, "unknown input dtype %d", (int)in_type);
-    const Variant *v = nullptr;
-    int rc = resolve_variant(p, direction, direction == DD_FORWARD ? in_type : DD_F32, &v);
+    std::vector<Block> blocks;
+    int rc = resolve_blocks(p, direction, direction == DD_FORWARD ? in_type : DD_F32, &blocks);
     if (rc != DD_OK)
         return rc;
-    const TileTables *t = nullptr;
-    return plan_tables(p, direction, *v, &t);
+    for (const Block &b : blocks) {
+        const TileTables *t = nullptr;
+        rc = plan_tables(p, direction, *find_variant(b.variant), &t, b.r0, b.r1);
+        if (rc != DD_OK)
+            return rc;
+    }
+    return DD_OK;
 }
 
 int dd_tile_count(int32_t *n_variants) {
@@ -160,6 +192,8 @@ int dd_plan_set_tile(dd_plan *p, dd_direction direction, dd_dtype in_type, int32
         return fail(DD_EINVAL, "unknown direction %d", (int)direction);
     if (in_type != DD_F32 && in_type != DD_F16 && in_type != DD_U8)
         return fail(DD_EINVAL, "unknown input dtype %d", (int)in_type);
+    if (direction == DD_ADJOINT && in_type != DD_F32)
+        return fail(DD_EINVAL, "the adjoint works on float32 only");
     if (variant != -1) {
         const Variant *v = find_variant(variant);
         if (!v)
@@ -173,6 +207,68 @@ int dd_plan_set_tile(dd_plan *p, dd_direction direction, dd_dtype in_type, int32
     }
     std::lock_guard<std::mutex> lock(p->mu);
     p->forced[direction][in_type] = variant;
+    p->blocks[direction][in_type].clear();
+    return DD_OK;
+}
+
+int dd_plan_set_blocks(dd_plan *p, dd_direction direction, dd_dtype in_type, int32_t n_blocks,
+                       const int32_t *row_starts, const int32_t *variants) {
+    clear_error();
+    if (!p)
+        return fail(DD_EINVAL, "plan is NULL");
+    if (direction != DD_FORWARD && direction != DD_ADJOINT)
+        return fail(DD_EINVAL, "unknown direction %d", (int)direction);
+    if (in_type != DD_F32 && in_type != DD_F16 && in_type != DD_U8)
+        return fail(DD_EINVAL, "unknown input dtype %d", (int)in_type);
+    if (direction == DD_ADJOINT && in_type != DD_F32)
+        return fail(DD_EINVAL, "the adjoint works on float32 only");
+    if (n_blocks < 1 || n_blocks > DD_MAX_BLOCKS || !row_starts || !variants)
+        return fail(DD_EINVAL, "need 1 <= n_blocks <= %d and both arrays", DD_MAX_BLOCKS);
+    const int32_t R = plan_rows(p, direction);
+    if (row_starts[0] != 0)
+        return fail(DD_EINVAL, "the first block must start at row 0");
+    std::vector<Block> blocks;
+    for (int32_t b = 0; b < n_blocks; ++b) {
+        const int32_t r0 = row_starts[b], r1 = b + 1 < n_blocks ? row_starts[b + 1] : R;
+        if (r1 <= r0 || r1 > R)
+            return fail(DD_EINVAL, "row starts must increase and stay below %d", R);
+        const Variant *v = find_variant(variants[b]);
+        if (!v)
+            return fail(DD_EINVAL, "unknown tile variant %d", variants[b]);
+        if (n_blocks > 1 && !block_capable(*v))
+            return fail(DD_EUNSUPPORTED, "tile variant %d cannot run a block of rows (direct kind)", v->id);
+        if (!has_kernel(*v, direction == DD_FORWARD ? (int32_t)in_type : (int32_t)DD_F32))
+            return fail(DD_EUNSUPPORTED, "this library has no kernel of tile variant %d for this input type", v->id);
+        if (!variant_fits(p, direction, *v, r0, r1))
+            return fail(DD_EUNSUPPORTED, "tile variant %d cannot serve rows [%d, %d) of this plan", v->id, r0, r1);
+        blocks.push_back(Block{r0, r1, v->id});
+    }
+    std::lock_guard<std::mutex> lock(p->mu);
+    p->forced[direction][in_type] = -1;
+    p->blocks[direction][in_type] = blocks;
+    return DD_OK;
+}
+
+int dd_plan_get_blocks(const dd_plan *p, dd_direction direction, dd_dtype in_type, int32_t *n_blocks,
+                       int32_t *row_starts, int32_t *variants) {
+    clear_error();
+    if (!p || !n_blocks)
+        return fail(DD_EINVAL, "NULL argument");
+    if (direction != DD_FORWARD && direction != DD_ADJOINT)
+        return fail(DD_EINVAL, "unknown direction %d", (int)direction);
+    if (in_type != DD_F32 && in_type != DD_F16 && in_type != DD_U8)
+        return fail(DD_EINVAL, "unknown input dtype %d", (int)in_type);
+    std::vector<Block> blocks;
+    int rc = resolve_blocks(p, direction, direction == DD_FORWARD ? in_type : DD_F32, &blocks);
+    if (rc != DD_OK)
+        return rc;
+    *n_blocks = static_cast<int32_t>(blocks.size());
+    for (size_t b = 0; b < blocks.size(); ++b) {
+        if (row_starts)
+            row_starts[b] = blocks[b].r0;
+        if (variants)
+            variants[b] = blocks[b].variant;
+    }
     return DD_OK;
 }
 
@@ -184,11 +280,15 @@ int dd_plan_get_tile(const dd_plan *p, dd_direction direction, dd_dtype in_type,
         return fail(DD_EINVAL, "unknown direction %d", (int)direction);
     if (in_type != DD_F32 && in_type != DD_F16 && in_type != DD_U8)
         return fail(DD_EINVAL, "unknown input dtype %d", (int)in_type);
-    const Variant *v = nullptr;
-    int rc = resolve_variant(p, direction, in_type, &v);
+    std::vector<Block> blocks;  // with a row split: the variant of its largest block
+    int rc = resolve_blocks(p, direction, direction == DD_FORWARD ? in_type : DD_F32, &blocks);
     if (rc != DD_OK)
         return rc;
-    *variant = v->id;
+    const Block *big = &blocks[0];
+    for (const Block &b : blocks)
+        if (b.r1 - b.r0 > big->r1 - big->r0)
+            big = &b;
+    *variant = big->variant;
     return DD_OK;
 }
 

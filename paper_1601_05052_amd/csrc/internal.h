@@ -75,6 +75,9 @@ struct SrsArgs {
     int32_t wcap;          // samples per staged row
     int32_t rows_per_chunk;
     int32_t lds_bytes;     // dynamic LDS per work-group
+    int32_t r_begin = 0;   // input rows [r_begin, r_end) summed by this launch
+    int32_t r_end = 0;
+    int32_t carry = 0;     // 1: continue the partial sums already in out
 };
 
 // Element types the kernels read.
@@ -103,6 +106,11 @@ hipError_t launch_srs(const Variant &v, int32_t in_type, const SrsArgs &a, hipSt
 // BeamDesc *, const uint32_t *items; 64 * waves threads per work-group), or
 // null where the library has none (the study library).
 const void *multi_kernel(const Variant &v, int32_t in_type);
+
+// One block of a row split: input rows [r0, r1) summed by `variant`.
+struct Block {
+    int32_t r0, r1, variant;
+};
 
 // Host-side layout of one (direction, variant) on one plan.
 struct Layout {
@@ -140,28 +148,40 @@ struct dd_plan {
     std::vector<int32_t> delay;  // [D][C]
 
     mutable std::mutex mu;
-    // (device, direction, variant id) -> device tables
-    mutable std::map<std::tuple<int, int, int>, dd::TileTables> tables;
-    // (direction, variant id) -> the same tables in host memory, kept once
-    // built (the allocation-free entry stages them into its own device array)
-    mutable std::map<std::pair<int, int>, dd::Layout> host_tables;
-    // (direction, variant id) -> (feasible, wcap, rows per chunk), host only
-    mutable std::map<std::pair<int, int>, std::tuple<bool, int32_t, int32_t>> fit;
+    // (device, direction, variant id, first row, end row) -> device tables of
+    // that block of input rows (the whole plan: rows [0, R))
+    mutable std::map<std::tuple<int, int, int, int, int>, dd::TileTables> tables;
+    // (direction, variant id, first row, end row) -> the same tables in host
+    // memory, kept once built (the allocation-free entry stages them into its
+    // own device array)
+    mutable std::map<std::tuple<int, int, int, int>, dd::Layout> host_tables;
+    // (direction, variant id, first row, end row) -> (feasible, wcap, rows per
+    // chunk), host only
+    mutable std::map<std::tuple<int, int, int, int>, std::tuple<bool, int32_t, int32_t>> fit;
     // forced tile per (direction, dtype); -1 = automatic
     int32_t forced[2][3] = {{-1, -1, -1}, {-1, -1, -1}};
     int32_t tuned[2][3] = {{-1, -1, -1}, {-1, -1, -1}};
+    // Row blocks per (direction, dtype), forced or tuned: the input rows split
+    // into consecutive blocks, each summed by its own variant in its own launch
+    // (later blocks continue the partial sums).  Empty: one variant for all.
+    // Used unless a single variant is forced; never by batches.
+    std::vector<dd::Block> blocks[2][3];
 };
 
 namespace dd {
 // Compute the layout of (direction, variant); arrays only if build_arrays.
-void compute_layout(const dd_plan *p, int direction, const Variant &v, bool build_arrays, Layout *L);
+// Tables for input rows [r0, r1) only (r1 < 0: every row); spans always cover
+// every row.
+void compute_layout(const dd_plan *p, int direction, const Variant &v, bool build_arrays, Layout *L,
+                    int32_t r0 = 0, int32_t r1 = -1);
 // Build (once) and return the device tables for (direction, variant) on the
 // current device.  Returns DD_OK or an error code.
-int plan_tables(const dd_plan *p, int direction, const Variant &v, const TileTables **out);
+int plan_tables(const dd_plan *p, int direction, const Variant &v, const TileTables **out, int32_t r0 = 0,
+                int32_t r1 = -1);
 // Variant the plan uses for (direction, dtype) when nothing is forced.
 int32_t default_variant(const dd_plan *p, int direction, int32_t in_type);
 // Whether variant v can serve (direction) of this plan (cached, host only).
-bool variant_fits(const dd_plan *p, int direction, const Variant &v);
+bool variant_fits(const dd_plan *p, int direction, const Variant &v, int32_t r0 = 0, int32_t r1 = -1);
 int32_t choose_variant(const dd_plan *p, int direction, int32_t in_type);
 // The variant a call uses: forced, else tuned, else the cost model's default.
 int32_t resolved_variant(const dd_plan *p, int direction, int32_t in_type);
@@ -169,17 +189,36 @@ int32_t resolved_variant(const dd_plan *p, int direction, int32_t in_type);
 int32_t best_by_model(const dd_plan *p, int direction, int32_t in_type, const int32_t *cand, int32_t n_cand);
 // Time the candidates on the plan's own sizes (scratch buffers allocated
 // here); best id and mean ms.  Synchronises the stream.
+// With split_out, row splits are timed too; *split_out receives the best
+// split if it beats the best single variant (else stays empty) and *best_ms
+// the time of what won.
 int tune_candidates(const dd_plan *p, int direction, int32_t in_type, int32_t reps, const int32_t *cand,
-                    int32_t n_cand, hipStream_t stream, int32_t *best, float *best_ms);
+                    int32_t n_cand, hipStream_t stream, int32_t *best, float *best_ms,
+                    std::vector<Block> *split_out = nullptr);
+// Free the device tables of row blocks of `direction` that `keep` does not
+// use (the tuner builds one per block and candidate).
+void release_block_tables(const dd_plan *p, int direction, const std::vector<Block> &keep);
 // Fill SrsArgs for one call (tables built on demand).
 int make_args(const dd_plan *p, int direction, const Variant &v, const void *in, int64_t in_stride,
-              float *out, int64_t out_stride, SrsArgs *a);
+              float *out, int64_t out_stride, SrsArgs *a, int32_t r0 = 0, int32_t r1 = -1);
 // The sizes and data pointers of SrsArgs for one call (no tables).
 void args_dims(const dd_plan *p, int direction, const void *in, int64_t in_stride, float *out, int64_t out_stride,
                SrsArgs *a);
 // Host copy of the tables of (direction, variant), or null if no call has
 // built them yet (dd_plan_prepare or a first compute call does).
-const Layout *plan_host_layout(const dd_plan *p, int direction, int32_t variant);
+const Layout *plan_host_layout(const dd_plan *p, int direction, int32_t variant, int32_t r0 = 0, int32_t r1 = -1);
+// Input rows of a direction (channels forward, DMs adjoint).
+int32_t plan_rows(const dd_plan *p, int direction);
+// Whether the variant's kind can run as one block of a row split (the
+// register-window and LDS kinds; the direct kind splits rows on its own).
+bool block_capable(const Variant &v);
+// The launches one call makes: the row blocks in use, else one block of
+// every row with the resolved variant.  Empty if no variant fits.
+std::vector<Block> launch_list(const dd_plan *p, int direction, int32_t in_type);
+// Run one call as the launch list: block b sums its rows with its variant,
+// continuing the partial sums of the blocks before it.
+int run_blocks(const dd_plan *p, int direction, int32_t in_type, const std::vector<Block> &blocks, const void *in,
+               int64_t in_stride, float *out, int64_t out_stride, hipStream_t stream);
 // Argument checks of the forward (api.cpp).
 int check_forward_args(const dd_plan *p, const void *d_in, int32_t in_type, int64_t in_stride, const float *d_out,
                        int64_t out_stride);

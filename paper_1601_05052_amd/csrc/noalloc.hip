@@ -19,6 +19,7 @@
 
 #include <cstdint>
 #include <mutex>
+#include <vector>
 
 #include "internal.h"
 
@@ -81,18 +82,24 @@ extern "C" int dd_dedisperse_noalloc(const dd_plan *p, const void *d_in, dd_dtyp
     int rc = check_forward_args(p, d_in, in_type, in_stride, d_out, out_stride);
     if (rc != DD_OK)
         return rc;
-    const Variant *v = find_variant(resolved_variant(p, DD_FORWARD, in_type));
-    if (!v)
+    const std::vector<Block> blocks = launch_list(p, DD_FORWARD, in_type);
+    if (blocks.empty())
         return fail(DD_EUNSUPPORTED, "no tile variant can serve this plan");
-    if (!has_kernel(*v, in_type))
-        return fail(DD_EUNSUPPORTED, "this library has no kernel of tile variant %d for this input type", v->id);
-    const Layout *L = plan_host_layout(p, DD_FORWARD, v->id);
-    if (!L)
-        return fail(DD_EINVAL,
-                    "the plan's forward tables for tile variant %d are not built: call dd_plan_prepare (or "
-                    "dd_dedisperse) once beforehand, where allocation is allowed", v->id);
-    const size_t need = aligned_bytes(L->base) + aligned_bytes(L->rel) + aligned_bytes(L->recs) +
-                        aligned_bytes(L->span);
+    // Every launch's tables (one per block of rows when the plan splits them).
+    std::vector<const Layout *> lays;
+    size_t need = 0;
+    for (const Block &b : blocks) {
+        const Variant *v = find_variant(b.variant);
+        if (!has_kernel(*v, in_type))
+            return fail(DD_EUNSUPPORTED, "this library has no kernel of tile variant %d for this input type", v->id);
+        const Layout *L = plan_host_layout(p, DD_FORWARD, v->id, b.r0, b.r1);
+        if (!L)
+            return fail(DD_EINVAL,
+                        "the plan's forward tables for tile variant %d are not built: call dd_plan_prepare (or "
+                        "dd_dedisperse) once beforehand, where allocation is allowed", v->id);
+        lays.push_back(L);
+        need += aligned_bytes(L->base) + aligned_bytes(L->rel) + aligned_bytes(L->recs) + aligned_bytes(L->span);
+    }
     if (need > kScratchBytes)
         return fail(DD_EUNSUPPORTED, "the tile tables need %zu bytes; the allocation-free entry holds at most %zu",
                     need, kScratchBytes);
@@ -103,19 +110,25 @@ extern "C" int dd_dedisperse_noalloc(const dd_plan *p, const void *d_in, dd_dtyp
     if (rc != DD_OK)
         return rc;
     hipStream_t stream = static_cast<hipStream_t>(stream_v);
-    SrsArgs a;
-    args_dims(p, DD_FORWARD, d_in, in_stride, d_out, out_stride, &a);
     size_t off = 0;
-    if ((rc = stage(L->base, base, &off, stream, &a.base)) != DD_OK ||
-        (rc = stage(L->rel, base, &off, stream, &a.rel)) != DD_OK ||
-        (rc = stage(L->recs, base, &off, stream, &a.recs)) != DD_OK ||
-        (rc = stage(L->span, base, &off, stream, &a.span)) != DD_OK)
-        return rc;
-    a.wcap = L->wcap;
-    a.rows_per_chunk = L->rows_per_chunk;
-    a.lds_bytes = L->lds_bytes;
-    const hipError_t e = launch_srs(*v, in_type, a, stream);
-    if (e != hipSuccess)
-        return fail(DD_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+    for (size_t i = 0; i < blocks.size(); ++i) {
+        const Layout *L = lays[i];
+        SrsArgs a;
+        args_dims(p, DD_FORWARD, d_in, in_stride, d_out, out_stride, &a);
+        a.r_begin = blocks[i].r0;
+        a.r_end = blocks[i].r1;
+        a.carry = blocks[i].r0 > 0 ? 1 : 0;
+        if ((rc = stage(L->base, base, &off, stream, &a.base)) != DD_OK ||
+            (rc = stage(L->rel, base, &off, stream, &a.rel)) != DD_OK ||
+            (rc = stage(L->recs, base, &off, stream, &a.recs)) != DD_OK ||
+            (rc = stage(L->span, base, &off, stream, &a.span)) != DD_OK)
+            return rc;
+        a.wcap = L->wcap;
+        a.rows_per_chunk = L->rows_per_chunk;
+        a.lds_bytes = L->lds_bytes;
+        const hipError_t e = launch_srs(*find_variant(blocks[i].variant), in_type, a, stream);
+        if (e != hipSuccess)
+            return fail(DD_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
+    }
     return DD_OK;
 }

@@ -72,19 +72,28 @@ static int64_t regwin_rows(const Variant &v, int32_t rows) {
     return (rows + cr - 1) / cr * cr;
 }
 
-void compute_layout(const dd_plan *p, int direction, const Variant &v, bool build, Layout *L) {
+void compute_layout(const dd_plan *p, int direction, const Variant &v, bool build, Layout *L, int32_t r0,
+                    int32_t r1) {
     const int32_t R = direction == DD_FORWARD ? p->C : p->D;
     const int32_t A = direction == DD_FORWARD ? p->D : p->C;
     const int32_t TA = v.ta(), TT = v.tt();
     const int32_t n_tiles = (A + TA - 1) / TA;
+    if (r1 < 0)
+        r1 = R;
+    const int32_t Rb = r1 - r0;  // rows of the block the tables hold (index r - r0)
     *L = Layout();
     L->n_tiles = n_tiles;
+    // A block must be non-empty and, for the staged kinds, start on a whole
+    // chunk of rows; the direct kind splits rows its own way (whole plans only).
+    const int32_t cr = v.kind == KIND_LDS && v.kmax == 0 ? 1 : v.waves * std::max(1, v.rpw);
+    if (r0 < 0 || r1 > R || r0 >= r1 || r0 % cr != 0 || (v.kind == KIND_DIRECT && (r0 != 0 || r1 != R)))
+        return;
     if (build) {
-        L->base.resize((size_t)n_tiles * R);
+        L->base.resize((size_t)n_tiles * Rb);
         if (v.kind != KIND_REGWIN)
-            L->rel.resize((size_t)n_tiles * R * TA);
+            L->rel.resize((size_t)n_tiles * Rb * TA);
         else  // rows padded to whole chunks; padding records stay zero
-            L->recs.assign((size_t)n_tiles * v.waves * regwin_rows(v, R) * regwin_rd(v), 0);
+            L->recs.assign((size_t)n_tiles * v.waves * regwin_rows(v, Rb) * regwin_rd(v), 0);
     }
     int32_t max_spread = 0;
     int32_t max_reach = 0;  // largest (offset - staged-row start) + 1 over rows and tiles
@@ -112,6 +121,13 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
                 lo = std::min(lo, o);
                 hi = std::max(hi, o);
             }
+            if (want_span) {  // spans cover every row; the rest only the block's
+                row_lo[r] = lo;
+                row_hi[r] = hi;
+            }
+            if (r < r0 || r >= r1)
+                continue;
+            const int32_t rb = r - r0;
             max_spread = std::max(max_spread, hi - lo);
             // Register-window rows start on a multiple of 4 samples, so the
             // staging's 16-byte loads are aligned for every input type
@@ -119,15 +135,11 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
             const int32_t b = v.kind == KIND_REGWIN ? lo - (((lo % 4) + 4) % 4) : lo;
             max_reach = std::max(max_reach, hi - b + 1);
             if (build)
-                L->base[(size_t)k * R + r] = b;
-            if (want_span) {
-                row_lo[r] = lo;
-                row_hi[r] = hi;
-            }
+                L->base[(size_t)k * Rb + rb] = b;
             if (v.kind != KIND_REGWIN) {
                 if (build)
                     for (int32_t j = 0; j < TA; ++j)
-                        L->rel[((size_t)k * R + r) * TA + j] = offset_of(p, direction, r, std::min(A - 1, k * TA + j)) - lo;
+                        L->rel[((size_t)k * Rb + rb) * TA + j] = offset_of(p, direction, r, std::min(A - 1, k * TA + j)) - lo;
                 continue;
             }
             const int32_t TDW = v.items_acc;
@@ -154,7 +166,7 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
                     const int32_t c = ws / 4;
                     const int32_t u_bytes = 16 * (S == 1 ? c : c + c / S);  // padded LDS layout
                     const int32_t RD = regwin_rd(v);
-                    int32_t *rec = &L->recs[(((size_t)k * v.waves + w) * regwin_rows(v, R) + r) * RD];
+                    int32_t *rec = &L->recs[(((size_t)k * v.waves + w) * regwin_rows(v, Rb) + rb) * RD];
                     rec[0] = u_bytes | (nq << 20);
                     for (int32_t j = 0; j < TDW; ++j) {
                         const uint32_t o = (uint32_t)(offset_of(p, direction, r, std::min(A - 1, k * TA + w * TDW + j)) -
@@ -231,17 +243,24 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
     L->feasible = true;
 }
 
-bool variant_fits(const dd_plan *p, int direction, const Variant &v) {
+int32_t plan_rows(const dd_plan *p, int direction) { return direction == DD_FORWARD ? p->C : p->D; }
+
+bool block_capable(const Variant &v) { return v.kind == KIND_REGWIN || v.kind == KIND_LDS; }
+
+bool variant_fits(const dd_plan *p, int direction, const Variant &v, int32_t r0, int32_t r1) {
+    if (r1 < 0)
+        r1 = plan_rows(p, direction);
+    const auto key = std::make_tuple(direction, (int)v.id, (int)r0, (int)r1);
     {
         std::lock_guard<std::mutex> lock(p->mu);
-        auto it = p->fit.find({direction, v.id});
+        auto it = p->fit.find(key);
         if (it != p->fit.end())
             return std::get<0>(it->second);
     }
     Layout L;
-    compute_layout(p, direction, v, false, &L);
+    compute_layout(p, direction, v, false, &L, r0, r1);
     std::lock_guard<std::mutex> lock(p->mu);
-    p->fit[{direction, v.id}] = std::make_tuple(L.feasible, L.wcap, L.rows_per_chunk);
+    p->fit[key] = std::make_tuple(L.feasible, L.wcap, L.rows_per_chunk);
     return L.feasible;
 }
 
@@ -268,10 +287,12 @@ static void free_tables(TileTables &t) {
     t = TileTables();
 }
 
-int plan_tables(const dd_plan *p, int direction, const Variant &v, const TileTables **out) {
+int plan_tables(const dd_plan *p, int direction, const Variant &v, const TileTables **out, int32_t r0, int32_t r1) {
+    if (r1 < 0)
+        r1 = plan_rows(p, direction);
     int dev = 0;
     DD_HIP_TRY(hipGetDevice(&dev));
-    const auto key = std::make_tuple(dev, direction, (int)v.id);
+    const auto key = std::make_tuple(dev, direction, (int)v.id, (int)r0, (int)r1);
     {
         std::lock_guard<std::mutex> lock(p->mu);
         auto it = p->tables.find(key);
@@ -282,7 +303,7 @@ int plan_tables(const dd_plan *p, int direction, const Variant &v, const TileTab
     }
     Layout L;
     try {
-        compute_layout(p, direction, v, true, &L);
+        compute_layout(p, direction, v, true, &L, r0, r1);
     } catch (const std::bad_alloc &) {
         return fail(DD_ENOMEM, "host allocation of tile tables failed");
     }
@@ -311,13 +332,40 @@ int plan_tables(const dd_plan *p, int direction, const Variant &v, const TileTab
     if (!ins.second)
         free_tables(t);  // another thread built it first
     *out = &ins.first->second;
-    p->host_tables.emplace(std::make_pair(direction, (int)v.id), std::move(L));
+    p->host_tables.emplace(std::make_tuple(direction, (int)v.id, (int)r0, (int)r1), std::move(L));
     return DD_OK;
 }
 
-const Layout *plan_host_layout(const dd_plan *p, int direction, int32_t variant) {
+void release_block_tables(const dd_plan *p, int direction, const std::vector<Block> &keep) {
+    const int32_t R = plan_rows(p, direction);
+    int cur = 0;
+    const bool have_dev = hipGetDevice(&cur) == hipSuccess;
     std::lock_guard<std::mutex> lock(p->mu);
-    auto it = p->host_tables.find({direction, (int)variant});
+    for (auto it = p->tables.begin(); it != p->tables.end();) {
+        const int dev = std::get<0>(it->first), dir = std::get<1>(it->first), id = std::get<2>(it->first);
+        const int r0 = std::get<3>(it->first), r1 = std::get<4>(it->first);
+        bool kept = dir != direction || (r0 == 0 && r1 == R);
+        for (const Block &b : keep)
+            kept = kept || (b.variant == id && b.r0 == r0 && b.r1 == r1);
+        if (kept) {
+            ++it;
+            continue;
+        }
+        if (have_dev)
+            (void)hipSetDevice(dev);
+        free_tables(it->second);
+        p->host_tables.erase(std::make_tuple(dir, id, r0, r1));
+        it = p->tables.erase(it);
+    }
+    if (have_dev)
+        (void)hipSetDevice(cur);
+}
+
+const Layout *plan_host_layout(const dd_plan *p, int direction, int32_t variant, int32_t r0, int32_t r1) {
+    if (r1 < 0)
+        r1 = plan_rows(p, direction);
+    std::lock_guard<std::mutex> lock(p->mu);
+    auto it = p->host_tables.find(std::make_tuple(direction, (int)variant, (int)r0, (int)r1));
     return it == p->host_tables.end() ? nullptr : &it->second;
 }
 
@@ -338,15 +386,23 @@ void args_dims(const dd_plan *p, int direction, const void *in, int64_t in_strid
         a->n_acc = p->C;
         a->n_rows = p->D;
     }
+    a->r_begin = 0;
+    a->r_end = a->n_rows;
+    a->carry = 0;
 }
 
 int make_args(const dd_plan *p, int direction, const Variant &v, const void *in, int64_t in_stride,
-              float *out, int64_t out_stride, SrsArgs *a) {
+              float *out, int64_t out_stride, SrsArgs *a, int32_t r0, int32_t r1) {
+    if (r1 < 0)
+        r1 = plan_rows(p, direction);
     const TileTables *t = nullptr;
-    int rc = plan_tables(p, direction, v, &t);
+    int rc = plan_tables(p, direction, v, &t, r0, r1);
     if (rc != DD_OK)
         return rc;
     args_dims(p, direction, in, in_stride, out, out_stride, a);
+    a->r_begin = r0;
+    a->r_end = r1;
+    a->carry = r0 > 0 ? 1 : 0;  // blocks run in row order
     a->rel = t->d_rel;
     a->base = t->d_base;
     a->recs = t->d_recs;

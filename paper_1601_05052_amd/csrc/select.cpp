@@ -42,7 +42,7 @@ int32_t best_by_model(const dd_plan *p, int direction, int32_t in_type, const in
         int32_t wcap = 0;
         {
             std::lock_guard<std::mutex> lock(p->mu);
-            wcap = std::get<1>(p->fit[{direction, v->id}]);
+            wcap = std::get<1>(p->fit[std::make_tuple(direction, (int)v->id, 0, (int)plan_rows(p, direction))]);
         }
         const double t = estimate_seconds(p, direction, *v, wcap);
         if (best < 0 || t < best_t) {
@@ -74,6 +74,18 @@ int32_t choose_variant(const dd_plan *p, int direction, int32_t in_type) {
 int32_t resolved_variant(const dd_plan *p, int direction, int32_t in_type) {
     const int32_t id = choose_variant(p, direction, in_type);
     return id == -2 ? default_variant(p, direction, in_type) : id;
+}
+
+std::vector<Block> launch_list(const dd_plan *p, int direction, int32_t in_type) {
+    {
+        std::lock_guard<std::mutex> lock(p->mu);
+        if (p->forced[direction][in_type] < 0 && !p->blocks[direction][in_type].empty())
+            return p->blocks[direction][in_type];
+    }
+    const int32_t id = resolved_variant(p, direction, in_type);
+    if (id < 0)
+        return {};
+    return {Block{0, plan_rows(p, direction), id}};
 }
 
 }  // namespace dd

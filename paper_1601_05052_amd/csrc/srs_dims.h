@@ -18,6 +18,12 @@ struct SrsDims {
     int32_t rows_per_chunk;
     int32_t n_t_tiles;
     int32_t n_acc_tiles;
+    // Input rows [r_begin, r_end) are summed (a block of a plan whose rows are
+    // split over several launches; r_begin is a multiple of the variant's rows
+    // per chunk).  carry: the sums continue the partial sums in the output.
+    int32_t r_begin;
+    int32_t r_end;
+    int32_t carry;
 };
 
 }  // namespace dev

@@ -194,7 +194,7 @@ struct ChunkStager {
     static constexpr int CR = NW * RPW;
     typedef typename QuadRaw<TIn>::T Raw;
     const TIn *in;
-    ctab *base_tile;
+    ctab *base_tile;  // staged-row starts of this tile, for rows [r_begin, r_end)
     const SrsDims &d;
     int64_t t0;
     int wave, lane;
@@ -214,9 +214,9 @@ struct ChunkStager {
 #pragma unroll
         for (int q = 0; q < RPW; ++q) {
             const int32_t row = c * CR + wave * RPW + q;
-            if (row < d.n_rows)
-                fetch_quads<TIn, KL>(in, d.in_stride, d.in_valid, row, t0 + base_tile[row], d.wcap, lane, raw[q],
-                                     &delta[q]);
+            if (row < d.r_end)
+                fetch_quads<TIn, KL>(in, d.in_stride, d.in_valid, row, t0 + base_tile[row - d.r_begin], d.wcap, lane,
+                                     raw[q], &delta[q]);
         }
     }
 
@@ -225,7 +225,7 @@ struct ChunkStager {
 #pragma unroll
         for (int q = 0; q < RPW; ++q) {
             const int32_t rr = wave * RPW + q;
-            if (c * CR + rr < d.n_rows) {
+            if (c * CR + rr < d.r_end) {
                 float *rowp = buf + rr * row_dw;
 #pragma unroll
                 for (int k = 0; k < KL; ++k) {
@@ -292,23 +292,42 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t t0 = static_cast<int64_t>(tile_t) * TT;
-    const int32_t n_chunks = (d.n_rows + CR - 1) / CR;
+    // The tables hold this launch's block of rows, [r_begin, r_end) (r_begin a
+    // multiple of CR): records for chunks c_first .. c_first + n_chunks - 1.
+    const int32_t c_first = d.r_begin / CR;
+    const int32_t n_chunks = (d.r_end - d.r_begin + CR - 1) / CR;
     ctab *rec_tile = recs + (static_cast<int64_t>(tile_a) * NW + wave) * n_chunks * (CR * RD);
-    // Chunks [c_lo, c_hi) hold every row with an operand inside the input
-    // for this tile; the rest would add only zeros (span: null = all rows).
-    int32_t c_lo = 0, c_hi = n_chunks;
+    // Chunks [c_lo, c_hi) hold the launch's block of rows; with a span, only
+    // those with an operand inside the input for this tile (the rest would add
+    // only zeros; span: null = all rows).
+    int32_t c_lo = c_first, c_hi = c_first + n_chunks;
     if (span) {
         const int64_t k = 2 * (static_cast<int64_t>(tile_a) * d.n_t_tiles + tile_t);
-        c_lo = __builtin_amdgcn_readfirstlane(span[k]) / CR;
-        c_hi = (__builtin_amdgcn_readfirstlane(span[k + 1]) + CR - 1) / CR;
+        c_lo = max(c_lo, __builtin_amdgcn_readfirstlane(span[k]) / CR);
+        c_hi = min(c_hi, (__builtin_amdgcn_readfirstlane(span[k + 1]) + CR - 1) / CR);
     }
 
     typename RW::Acc acc;
 #pragma unroll
     for (int i = 0; i < IT * TDW; ++i)
         RW::set_acc(acc, i, 0.f);
+    if (d.carry) {  // continue the partial sums of the previous blocks
+        const int64_t tl = t0 + static_cast<int64_t>(lane) * IT;
+#pragma unroll
+        for (int a = 0; a < TDW; ++a) {
+            const int32_t ag = tile_a * TA + wave * TDW + a;
+            if (ag < d.n_acc) {
+                const float *src = out + static_cast<int64_t>(ag) * d.out_stride + tl;
+#pragma unroll
+                for (int j = 0; j < IT; ++j)
+                    if (tl + j < d.n_t)
+                        RW::set_acc(acc, a * IT + j, src[j]);
+            }
+        }
+    }
 
-    ChunkStager<TIn, S, NW, RPW, KMAX> st(in, base + static_cast<int64_t>(tile_a) * d.n_rows, d, t0, wave, lane);
+    ChunkStager<TIn, S, NW, RPW, KMAX> st(in, base + static_cast<int64_t>(tile_a) * (d.r_end - d.r_begin), d, t0,
+                                          wave, lane);
     const int32_t buf_dw = CR * st.row_dw;  // two chunk buffers
     const uint32_t lane_rd = lds_address(lds) + static_cast<uint32_t>(lane) * 16u * (S == 1 ? 1u : S + 1u);
 
@@ -322,7 +341,7 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
     const int32_t n_groups = c_hi * 2;
     uint32_t rs0[G * RD], rs1[G * RD];
     auto load_recs = [&](uint32_t (&r)[G * RD], int32_t g, int dep) {
-        ctab *p = rec_tile + static_cast<int64_t>(g) * (G * RD) + dep;
+        ctab *p = rec_tile + static_cast<int64_t>(g - 2 * c_first) * (G * RD) + dep;
 #pragma unroll
         for (int i = 0; i < G * RD; ++i)
             r[i] = static_cast<uint32_t>(p[i]);
@@ -337,7 +356,7 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
     __syncthreads();  // first chunk staged
     for (int32_t c = c_lo; c < c_hi; ++c) {
         const int32_t r0 = c * CR;
-        const int32_t nr = min(CR, d.n_rows - r0);
+        const int32_t nr = min(CR, d.r_end - r0);
         const uint32_t chunk_rd = lane_rd + static_cast<uint32_t>((c & 1) * buf_dw) * 4u;
 #pragma unroll
         for (int rr = 0; rr < CR; ++rr) {
@@ -390,33 +409,43 @@ __device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t t0 = static_cast<int64_t>(tile_t) * TT;
-    ctab *base_tile = base + static_cast<int64_t>(tile_a) * d.n_rows;
-    ctab *rel_tile = rel + static_cast<int64_t>(tile_a) * d.n_rows * TA + wave * TDW;
+    // The tables hold this launch's block of rows, [r_begin, r_end).
+    const int32_t nb = d.r_end - d.r_begin;
+    ctab *base_tile = base + static_cast<int64_t>(tile_a) * nb;
+    ctab *rel_tile = rel + static_cast<int64_t>(tile_a) * nb * TA + wave * TDW;
     const int32_t nk = d.wcap >> 6;
     const int32_t buf_dw = CR * d.wcap;
 
     float acc[TDW][IT];
 #pragma unroll
-    for (int k = 0; k < TDW; ++k)
+    for (int k = 0; k < TDW; ++k) {
+        const int32_t ag = tile_a * TA + wave * TDW + k;
 #pragma unroll
-        for (int j = 0; j < IT; ++j)
-            acc[k][j] = 0.f;
+        for (int j = 0; j < IT; ++j) {
+            const int64_t t = t0 + lane + 64 * j;
+            // carry: continue the partial sums of the previous blocks of rows
+            acc[k][j] = d.carry && ag < d.n_acc && t < d.n_t ? out[static_cast<int64_t>(ag) * d.out_stride + t] : 0.f;
+        }
+    }
 
     float pre[RPW][KMAX];
-    const int32_t n_chunks = (d.n_rows + CR - 1) / CR;
+    // This launch's block of rows: chunks [c_first, n_chunks).
+    const int32_t c_first = d.r_begin / CR;
+    const int32_t n_chunks = (d.r_end + CR - 1) / CR;
     auto fetch_chunk = [&](int32_t c) {
 #pragma unroll
         for (int q = 0; q < RPW; ++q) {
             const int32_t row = c * CR + wave * RPW + q;
-            if (row < d.n_rows)
-                fetch_row<TIn, KMAX>(in, d.in_stride, d.in_valid, row, t0 + base_tile[row], nk, lane, pre[q]);
+            if (row < d.r_end)
+                fetch_row<TIn, KMAX>(in, d.in_stride, d.in_valid, row, t0 + base_tile[row - d.r_begin], nk, lane,
+                                     pre[q]);
         }
     };
     auto store_chunk = [&](int32_t c) {
 #pragma unroll
         for (int q = 0; q < RPW; ++q) {
             const int32_t rr = wave * RPW + q;
-            if (c * CR + rr < d.n_rows) {
+            if (c * CR + rr < d.r_end) {
                 float *dst = lds + (c & 1) * buf_dw + rr * d.wcap + lane;
 #pragma unroll
                 for (int k = 0; k < KMAX; ++k)
@@ -442,7 +471,7 @@ __device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float 
         if constexpr (PREF) {
 #pragma unroll
         for (int rr = 0; rr < CR; ++rr) {
-            const int32_t r = min(c * CR + rr, d.n_rows - 1);
+            const int32_t r = min(c * CR + rr, d.r_end - 1) - d.r_begin;
             const uint32_t off = static_cast<uint32_t>(r * TA) * 4u;  // within this tile's table
             if constexpr (TDW % 4 == 0) {
 #pragma unroll
@@ -462,19 +491,19 @@ __device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float 
         }
     };
 
-    fetch_chunk(0);
-    store_chunk(0);
-    if (n_chunks > 1)
-        fetch_chunk(1);
+    fetch_chunk(c_first);
+    store_chunk(c_first);
+    if (c_first + 1 < n_chunks)
+        fetch_chunk(c_first + 1);
     if constexpr (PREF) {
-        load_offsets(onxt, 0);
-        if (n_chunks > 1)
-            load_offsets(onxt2, 1);
+        load_offsets(onxt, c_first);
+        if (c_first + 1 < n_chunks)
+            load_offsets(onxt2, c_first + 1);
     }
     __syncthreads();
-    for (int32_t c = 0; c < n_chunks; ++c) {
+    for (int32_t c = c_first; c < n_chunks; ++c) {
         const int32_t r0 = c * CR;
-        const int32_t nr = min(CR, d.n_rows - r0);
+        const int32_t nr = min(CR, d.r_end - r0);
         const float *buf = lds + (c & 1) * buf_dw + lane;
 #pragma unroll
         for (int rr = 0; rr < OR; ++rr)
@@ -494,7 +523,7 @@ __device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float 
                 if constexpr (PREF)
                     ok = ocur[rr % OR][k % OK];
                 else
-                    ok = __builtin_amdgcn_readfirstlane(rel_tile[static_cast<int64_t>(r0 + rr) * TA + k]);
+                    ok = __builtin_amdgcn_readfirstlane(rel_tile[static_cast<int64_t>(r0 - d.r_begin + rr) * TA + k]);
                 const float *p = row + ok;
 #pragma unroll
                 for (int j = 0; j < IT; ++j)

@@ -59,22 +59,29 @@ __device__ __forceinline__ void srs_tile_lds(const TIn *__restrict__ in, float *
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t t0 = static_cast<int64_t>(tile_t) * TT;
-    ctab *rel_tile = rel + static_cast<int64_t>(tile_a) * d.n_rows * TA + wave * TDW;
-    ctab *base_tile = base + static_cast<int64_t>(tile_a) * d.n_rows;
+    // The tables hold this launch's block of rows, [r_begin, r_end).
+    const int32_t nb = d.r_end - d.r_begin;
+    ctab *rel_tile = rel + static_cast<int64_t>(tile_a) * nb * TA + wave * TDW;
+    ctab *base_tile = base + static_cast<int64_t>(tile_a) * nb;
 
     float acc[TDW][IT];
 #pragma unroll
-    for (int k = 0; k < TDW; ++k)
+    for (int k = 0; k < TDW; ++k) {
+        const int32_t ag = tile_a * TA + wave * TDW + k;
 #pragma unroll
-        for (int j = 0; j < IT; ++j)
-            acc[k][j] = 0.f;
+        for (int j = 0; j < IT; ++j) {
+            const int64_t t = t0 + lane + 64 * j;
+            // carry: continue the partial sums of the previous blocks of rows
+            acc[k][j] = d.carry && ag < d.n_acc && t < d.n_t ? out[static_cast<int64_t>(ag) * d.out_stride + t] : 0.f;
+        }
+    }
 
-    for (int32_t r0 = 0; r0 < d.n_rows; r0 += d.rows_per_chunk) {
-        const int32_t nr = min(d.rows_per_chunk, d.n_rows - r0);
+    for (int32_t r0 = d.r_begin; r0 < d.r_end; r0 += d.rows_per_chunk) {  // this launch's block of rows
+        const int32_t nr = min(d.rows_per_chunk, d.r_end - r0);
         __syncthreads();  // previous chunk fully consumed
         for (int32_t rr = wave; rr < nr; rr += NW) {
             const int32_t r = r0 + rr;
-            const int64_t g0 = t0 + base_tile[r];
+            const int64_t g0 = t0 + base_tile[r - d.r_begin];
             const TIn *src = in + static_cast<int64_t>(r) * d.in_stride;
             float *dst = lds + rr * d.wcap;
 #pragma unroll 4
@@ -88,7 +95,7 @@ __device__ __forceinline__ void srs_tile_lds(const TIn *__restrict__ in, float *
         }
         __syncthreads();  // window staged
         for (int32_t rr = 0; rr < nr; ++rr) {
-            ctab *o = rel_tile + static_cast<int64_t>(r0 + rr) * TA;
+            ctab *o = rel_tile + static_cast<int64_t>(r0 - d.r_begin + rr) * TA;
             const float *row = lds + rr * d.wcap + lane;
 #pragma unroll
             for (int k = 0; k < TDW; ++k) {

@@ -63,7 +63,9 @@ std::string cache_key(const dd_plan *p, int direction, int32_t in_type) {
     return buf;
 }
 
-bool cache_lookup(const char *path, const std::string &key, int32_t *variant, float *ms) {
+// Cache lines: "key variant ms" or "key variant ms r0:v,r0:v,..." (a row split).
+bool cache_lookup(const char *path, const std::string &key, int32_t *variant, float *ms,
+                  std::vector<std::pair<int32_t, int32_t>> *split) {
     std::ifstream f(path);
     if (!f)
         return false;
@@ -71,30 +73,83 @@ bool cache_lookup(const char *path, const std::string &key, int32_t *variant, fl
     bool found = false;
     while (std::getline(f, line)) {
         std::istringstream ss(line);
-        std::string k;
+        std::string k, blocks;
         int32_t v;
         float t;
         if (ss >> k >> v >> t && k == key && find_variant(v)) {
             *variant = v;
             *ms = t;
+            split->clear();
+            if (ss >> blocks) {
+                std::istringstream bs(blocks);
+                std::string item;
+                while (std::getline(bs, item, ',')) {
+                    int32_t r0 = -1, bv = -1;
+                    if (std::sscanf(item.c_str(), "%d:%d", &r0, &bv) == 2 && find_variant(bv))
+                        split->emplace_back(r0, bv);
+                }
+            }
             found = true;  // last entry wins
         }
     }
     return found;
 }
 
-void cache_store(const char *path, const std::string &key, int32_t variant, float ms) {
+void cache_store(const char *path, const std::string &key, int32_t variant, float ms, const std::vector<Block> &split) {
     std::ofstream f(path, std::ios::app);
-    if (f)
-        f << key << ' ' << variant << ' ' << ms << '\n';
+    if (!f)
+        return;
+    f << key << ' ' << variant << ' ' << ms;
+    for (size_t b = 0; b < split.size(); ++b)
+        f << (b ? ',' : ' ') << split[b].r0 << ':' << split[b].variant;
+    f << '\n';
 }
 
 }  // namespace
 
 namespace dd {
 
+// Mean milliseconds of `reps` runs of one launch list, after one warm-up run.
+static int time_blocks(const dd_plan *p, int direction, int32_t in_t, const std::vector<Block> &blocks, int32_t reps,
+                       const void *d_in, int64_t in_cols, float *d_out, int64_t out_cols, hipStream_t stream,
+                       hipEvent_t e0, hipEvent_t e1, float *ms) {
+    int rc = run_blocks(p, direction, in_t, blocks, d_in, in_cols, d_out, out_cols, stream);
+    if (rc != DD_OK)
+        return rc;
+    (void)hipEventRecord(e0, stream);
+    for (int32_t r = 0; r < reps && rc == DD_OK; ++r)
+        rc = run_blocks(p, direction, in_t, blocks, d_in, in_cols, d_out, out_cols, stream);
+    (void)hipEventRecord(e1, stream);
+    if (hipEventSynchronize(e1) != hipSuccess)
+        return fail(DD_EHIP, "tuning run failed");
+    (void)hipEventElapsedTime(ms, e0, e1);
+    *ms /= reps;
+    return rc;
+}
+
+// Row splits tried by the tuner: the rows cut into 2, 3 or 4 blocks of about
+// equal size at multiples of 64 rows (a multiple of every variant's rows per
+// chunk); every block is timed alone with every variant that can serve it.
+static std::vector<std::vector<int32_t>> split_candidates(int32_t R) {
+    std::vector<std::vector<int32_t>> out;
+    if (R < 256)
+        return out;
+    for (int32_t nb = 2; nb <= 4; ++nb) {
+        std::vector<int32_t> starts{0};
+        for (int32_t k = 1; k < nb; ++k) {
+            const int32_t r = static_cast<int32_t>(static_cast<int64_t>(R) * k / nb) / 64 * 64;
+            if (r > starts.back() && r < R)
+                starts.push_back(r);
+        }
+        if (starts.size() == static_cast<size_t>(nb))
+            out.push_back(starts);
+    }
+    return out;
+}
+
 int tune_candidates(const dd_plan *p, int direction, int32_t in_type, int32_t reps, const int32_t *cand,
-                    int32_t n_cand, hipStream_t stream, int32_t *best_out, float *best_ms_out) {
+                    int32_t n_cand, hipStream_t stream, int32_t *best_out, float *best_ms_out,
+                    std::vector<Block> *split_out) {
     const size_t esz = direction == DD_ADJOINT ? 4 : (in_type == DD_F32 ? 4 : in_type == DD_F16 ? 2 : 1);
     const int64_t in_rows = direction == DD_FORWARD ? p->C : p->D;
     const int64_t in_cols = direction == DD_FORWARD ? p->T_in : p->S;
@@ -144,6 +199,51 @@ int tune_candidates(const dd_plan *p, int direction, int32_t in_type, int32_t re
                 best_t = ms;
             }
         }
+        if (rc != DD_OK || best < 0 || !split_out)
+            break;
+        // Row splits: each block's fastest variant, timed alone; the split
+        // replaces the single variant only if it is faster by more than 2%.
+        const int32_t R = plan_rows(p, direction);
+        float split_t = 0.98f * best_t;
+        for (const std::vector<int32_t> &starts : split_candidates(R)) {
+            std::vector<Block> blocks;
+            float total = 0.f;
+            for (size_t b = 0; b < starts.size() && rc == DD_OK; ++b) {
+                const int32_t r0 = starts[b], r1 = b + 1 < starts.size() ? starts[b + 1] : R;
+                Block bb{r0, r1, -1};
+                float bb_t = 0.f;
+                for (int32_t i = 0; i < n_cand && rc == DD_OK; ++i) {
+                    const Variant *v = find_variant(cand[i]);
+                    if (!v || !block_capable(*v) || !has_kernel(*v, in_t) || !variant_fits(p, direction, *v, r0, r1))
+                        continue;
+                    float ms = 0.f;
+                    rc = time_blocks(p, direction, in_t, {Block{r0, r1, v->id}}, reps, d_in, in_cols, d_out, out_cols,
+                                     stream, e0, e1, &ms);
+                    if (rc == DD_OK && (bb.variant < 0 || ms < bb_t)) {
+                        bb.variant = v->id;
+                        bb_t = ms;
+                    }
+                }
+                if (bb.variant < 0)
+                    break;
+                blocks.push_back(bb);
+                total += bb_t;
+            }
+            if (rc != DD_OK)
+                break;
+            if (blocks.size() == starts.size() && total < split_t) {
+                // Confirm the split as one call (the blocks back to back).
+                float ms = 0.f;
+                rc = time_blocks(p, direction, in_t, blocks, reps, d_in, in_cols, d_out, out_cols, stream, e0, e1, &ms);
+                if (rc == DD_OK && ms < split_t) {
+                    *split_out = blocks;
+                    split_t = ms;
+                }
+            }
+        }
+        if (rc == DD_OK && !split_out->empty())
+            best_t = split_t;
+        release_block_tables(p, direction, *split_out);
     } while (false);
     if (e0)
         (void)hipEventDestroy(e0);
@@ -180,12 +280,14 @@ static int check_tune_args(const dd_plan *p, int direction, int in_type, int32_t
 namespace {
 
 // Tune one (plan, direction, dtype): the cache file first, then `memo` (plans
-// of the same shape tuned earlier in this call), else time every variant.
+// of the same shape tuned earlier in this call), else time every variant and,
+// if `splits`, row splits (batches use one variant per beam: no splits).
 int tune_one(dd_plan *p, int direction, int32_t in_type, int32_t reps, const char *cache_path, hipStream_t stream,
-             std::map<std::string, std::pair<int32_t, float>> *memo, int32_t *best_out, float *ms_out) {
-    const std::string key = cache_key(p, direction, in_type);
+             std::map<std::string, std::pair<int32_t, float>> *memo, bool splits, int32_t *best_out, float *ms_out) {
+    const std::string key = cache_key(p, direction, in_type) + (splits ? "_split" : "");
     int32_t best = -1;
     float best_t = 0.f;
+    std::vector<Block> split;
     bool have = false;
     if (memo) {
         auto it = memo->find(key);
@@ -195,26 +297,48 @@ int tune_one(dd_plan *p, int direction, int32_t in_type, int32_t reps, const cha
             have = true;
         }
     }
-    if (!have && cache_path && cache_lookup(cache_path, key, &best, &best_t) &&
-        variant_fits(p, direction, *find_variant(best)))
+    std::vector<std::pair<int32_t, int32_t>> cached;
+    if (!have && cache_path && cache_lookup(cache_path, key, &best, &best_t, &cached) &&
+        variant_fits(p, direction, *find_variant(best))) {
         have = true;
+        const int32_t R = plan_rows(p, direction);
+        for (size_t b = 0; b < cached.size() && have; ++b) {
+            const int32_t r0 = cached[b].first, r1 = b + 1 < cached.size() ? cached[b + 1].first : R;
+            const Variant *v = find_variant(cached[b].second);
+            if (!block_capable(*v) || !variant_fits(p, direction, *v, r0, r1))
+                have = false;
+            split.push_back(Block{r0, r1, v->id});
+        }
+        if (!have)
+            split.clear();
+    }
     if (!have) {
         int32_t n = 0;
         variants(&n);
         std::vector<int32_t> all(n);
         for (int32_t i = 0; i < n; ++i)
             all[i] = i;
-        int rc = tune_candidates(p, direction, in_type, reps, all.data(), n, stream, &best, &best_t);
+        int rc = tune_candidates(p, direction, in_type, reps, all.data(), n, stream, &best, &best_t,
+                                 splits ? &split : nullptr);
         if (rc != DD_OK)
             return rc;
         if (cache_path)
-            cache_store(cache_path, key, best, best_t);
+            cache_store(cache_path, key, best, best_t, split);
     }
     if (memo)
         (*memo)[key] = std::make_pair(best, best_t);
     {
         std::lock_guard<std::mutex> lock(p->mu);
         p->tuned[direction][in_type] = best;
+        p->blocks[direction][in_type] = split;
+    }
+    // Report what a call now uses: with a split, its largest block's variant.
+    if (!split.empty()) {
+        const Block *big = &split[0];
+        for (const Block &b : split)
+            if (b.r1 - b.r0 > big->r1 - big->r0)
+                big = &b;
+        best = big->variant;
     }
     *best_out = best;
     *ms_out = best_t;
@@ -231,7 +355,7 @@ extern "C" int dd_autotune(dd_plan *p, dd_direction direction, dd_dtype in_type,
         return rc;
     int32_t best = -1;
     float best_t = 0.f;
-    rc = tune_one(p, direction, in_type, reps, cache_path, static_cast<hipStream_t>(stream_v), nullptr, &best,
+    rc = tune_one(p, direction, in_type, reps, cache_path, static_cast<hipStream_t>(stream_v), nullptr, true, &best,
                   &best_t);
     if (rc != DD_OK)
         return rc;
@@ -256,7 +380,7 @@ extern "C" int dd_batch_autotune(dd_plan *const *plans, int32_t n_beams, dd_dtyp
     for (int32_t b = 0; b < n_beams; ++b) {
         int32_t best = -1;
         float best_t = 0.f;
-        int rc = tune_one(plans[b], DD_FORWARD, in_type, reps, cache_path, static_cast<hipStream_t>(stream_v), &memo,
+        int rc = tune_one(plans[b], DD_FORWARD, in_type, reps, cache_path, static_cast<hipStream_t>(stream_v), &memo, false,
                           &best, &best_t);
         if (rc != DD_OK)
             return rc;

@@ -277,3 +277,41 @@ def test_noalloc_entry_refuses_unprepared_plan_before_gpu_work():
                                    None) == _lib.DD_ESHAPE
     assert L.dd_dedisperse_noalloc(None, ctypes.addressof(buf_in), 0, T, ctypes.addressof(buf_out), 10,
                                    None) == _lib.DD_EINVAL
+
+
+def test_row_split_arguments_checked_on_the_host():
+    """dd_plan_set_blocks validates starts, ids and fit on the host; get_blocks
+    reports one block without a split and the split after one is set."""
+    from paper_1601_05052_amd import DD_ADJOINT, DD_FORWARD
+    p = Plan(64, 1400.0, 1.5625, 5e-5, 0.0, 0.5, 128, 4096)
+    kinds = {v[0]: v[4] for v in tile_variants()}
+    assert len(p.get_blocks()) == 1 and p.get_blocks()[0][0] == 0
+    p.set_blocks([0, 32], [9, 0])
+    assert p.get_blocks() == [(0, 9), (32, 0)]
+    assert p.get_tile() in (9, 0)
+    for starts, vs in (([16, 32], [9, 9]),      # must start at row 0
+                       ([0, 32, 16], [9, 9, 9]),  # must increase
+                       ([0, 64], [9, 9]),       # past the last row (64 channels)
+                       ([0, 32], [9, 10 ** 6])):  # unknown variant
+        with pytest.raises(DedispError) as e:
+            p.set_blocks(starts, vs)
+        assert e.value.code == _lib.DD_EINVAL, (starts, vs)
+    direct = next(v for v, k in kinds.items() if k == 2)
+    with pytest.raises(DedispError) as e:
+        p.set_blocks([0, 32], [9, direct])
+    assert e.value.code == _lib.DD_EUNSUPPORTED
+    regwin = next(v for v, k in kinds.items() if k == 1)
+    with pytest.raises(DedispError) as e:   # a block start off its chunk of rows
+        p.set_blocks([0, 1], [9, regwin])
+    assert e.value.code == _lib.DD_EUNSUPPORTED
+    p.set_tile(0)                         # a forced single variant replaces the split
+    assert p.get_blocks() == [(0, 0)]
+    p.set_blocks([0, 64], [9, 9], direction=DD_ADJOINT)   # adjoint rows are the 128 DMs
+    assert p.get_blocks(direction=DD_ADJOINT) == [(0, 9), (64, 9)]
+    assert p.get_blocks(direction=DD_FORWARD) == [(0, 0)]
+    from paper_1601_05052_amd import DD_U8
+    for call in (lambda: p.set_blocks([0, 64], [9, 9], direction=DD_ADJOINT, dtype=DD_U8),
+                 lambda: p.set_tile(9, direction=DD_ADJOINT, dtype=DD_U8)):
+        with pytest.raises(DedispError) as e:   # the adjoint works on float32 rows only
+            call()
+        assert e.value.code == _lib.DD_EINVAL
