@@ -42,7 +42,7 @@ ADD_PEAK_TFLOPS = 256 * 128 * 2.4e9 / 1e12
 
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ["paper_1601_05052_amd/csrc/" + n for n in (
-    "srs_regwin.h", "regwin_asm.h", "srs_tile.h", "srs_launch.h", "srs_inst.inc", "srs_kernels_f32.hip",
+    "srs_regwin.h", "regwin_asm.h", "srs_tile.h", "srs_dims.h", "srs_launch.h", "srs_inst.inc", "srs_kernels_f32.hip",
     "variants.cpp", "plan.cpp")]
 VARIANT_LIST = "paper_1601_05052_amd/csrc/srs_variants.def"
 

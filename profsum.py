@@ -12,9 +12,26 @@
 
     python3 profsum.py counters FETCH_DIR WRITE_DIR KERNEL [--copy-bytes N]
         FETCH_SIZE and WRITE_SIZE (KiB per dispatch, two rocprofv3 --pmc runs)
-        of the matching kernels, scaled by what the same counters read for the
-        device-to-device copy of N bytes (default 256 MiB) in the same run,
-        whose kernel name contains "copyBuffer".
+        of the matching kernels, over all dispatches and over the timed calls
+        only (dispatches right after the 1 GiB scratch write), scaled by what
+        the same counters read for the device-to-device copy of N bytes
+        (default 256 MiB) in the same run, whose kernel name contains
+        "copyBuffer".
+
+    python3 profsum.py traffic FETCH_DIR WRITE_DIR WORKLOAD VARIANT [--copy-bytes N]
+        JSON on stdout for profiles/traffic_<workload>_fwd.json: the calibrated
+        HBM-side bytes per launch of every tile variant whose kernel ran in the
+        two counter runs (the timed calls where there are any, else the first
+        pass of the autotuner, which times the variants in id order over all
+        rows before it tries row splits), keyed by
+        variant id, with the variant's entry in the variant list and the hash
+        of the kernel sources (bench.py uses the bytes only while both match).
+        Variants whose kernel name another variant shares are left out.
+
+    python3 profsum.py variants TRACE_DIR TRAFFIC_JSON
+        Per tile variant the autotuner timed over all rows in the traced
+        program (its first pass, variants in id order): the mean dispatch
+        duration, and the bytes per launch from TRAFFIC_JSON.
 
     python3 profsum.py study JSON [--curated N]
         The auto-tuning study (bench.py --tune-study): per instance the
@@ -95,18 +112,63 @@ def trace(directory, kernel, flush):
           "per call average %.0f ns, min %d, max %d, std %.0f." % (c, "/".join(map(str, per)), avg, lo, hi, sd))
 
 
-def _counter(directory, name):
-    """{kernel name: [value per dispatch]} of one counter."""
+def _counter_seq(directory, name):
+    """[(kernel name, value)] of one counter, one entry per dispatch, in
+    dispatch order (a counter summed over its dimensions)."""
     vals = {}
     for r in _rows(directory, "counter_collection.csv"):
         if r.get("Counter_Name") != name:
             continue
-        vals.setdefault(r["Kernel_Name"], {}).setdefault(r.get("Dispatch_Id", len(vals)), 0.0)
-        vals[r["Kernel_Name"]][r.get("Dispatch_Id")] += float(r["Counter_Value"])
-    return {k: list(v.values()) for k, v in vals.items()}
+        d = int(r["Dispatch_Id"])
+        k, v = vals.get(d, (r["Kernel_Name"], 0.0))
+        vals[d] = (k, v + float(r["Counter_Value"]))
+    return [vals[d] for d in sorted(vals)]
 
 
-def counters(fetch_dir, write_dir, kernel, copy_bytes):
+def _counter(directory, name):
+    """{kernel name: [value per dispatch]} of one counter."""
+    out = {}
+    for k, v in _counter_seq(directory, name):
+        out.setdefault(k, []).append(v)
+    return out
+
+
+def _after_flush(seq, kernel, flush):
+    """Values of the dispatches of `kernel` that directly follow a dispatch
+    whose name contains `flush` (bench.py's timed calls)."""
+    return [v for (pk, _), (k, v) in zip(seq, seq[1:]) if k == kernel and flush in pk]
+
+
+def _tuning_runs(seq, owners):
+    """{variant id: [values]} of the autotuner's first pass: it times the
+    variants in id order, each over all rows, before it tries row splits, so
+    the pass ends where a kernel of a lower id than the previous one runs.
+    `owners` maps a kernel key to the variant ids that instantiate it; kernels
+    shared by several variants are skipped."""
+    out, last = {}, -1
+    for name, v in seq:
+        key = _kernel_key(name)
+        if key is None or "<float," not in name or len(owners.get(key, [])) != 1:
+            continue
+        vid = owners[key][0]
+        if vid < last:
+            break
+        last = vid
+        out.setdefault(vid, []).append(v)
+    return out
+
+
+def _owners(here):
+    sys.path.insert(0, here)
+    import bench  # the variant list bench.py and the library use
+    owners = {}
+    for vid, key in _variant_kernels(os.path.join(here, bench.VARIANT_LIST)).items():
+        owners.setdefault(key, []).append(vid)
+    return owners
+
+
+def counters(fetch_dir, write_dir, kernel, copy_bytes, flush):
+    fseq, wseq = _counter_seq(fetch_dir, "FETCH_SIZE"), _counter_seq(write_dir, "WRITE_SIZE")
     fetch, write = _counter(fetch_dir, "FETCH_SIZE"), _counter(write_dir, "WRITE_SIZE")
     copy_kib = copy_bytes / 1024.0
 
@@ -120,25 +182,118 @@ def counters(fetch_dir, write_dir, kernel, copy_bytes):
         raise SystemExit("no copyBuffer dispatches to calibrate against")
     f_scale = copy_kib / statistics.median(cf)
     w_scale = copy_kib / statistics.median(cw)
-    print("| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | dispatches (fetch / write) |")
-    print("|---|---|---|---|")
     names = sorted({k for k in list(fetch) + list(write) if kernel in k})
     if not names:
         raise SystemExit("no kernel matching %r" % kernel)
+    print("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | timed calls | FETCH_SIZE KiB | WRITE_SIZE KiB |")
+    print("|---|---|---|---|---|---|---|")
+    mean = lambda v: statistics.mean(v) if v else float("nan")  # noqa: E731
     for n in names:
         f, w = fetch.get(n, []), write.get(n, [])
-        print("| `%s` | %.1f | %.1f | %d / %d |" % (n, statistics.mean(f) if f else float("nan"),
-                                                    statistics.mean(w) if w else float("nan"), len(f), len(w)))
-    print("| copy of %d MiB (`copyBuffer`) | %.1f | %.1f | %d / %d |" % (
-        copy_bytes >> 20, statistics.median(cf), statistics.median(cw), len(cf), len(cw)))
+        tf, tw = _after_flush(fseq, n, flush), _after_flush(wseq, n, flush)
+        print("| `%s` | %d / %d | %.1f | %.1f | %d / %d | %.1f | %.1f |" % (
+            n, len(f), len(w), mean(f), mean(w), len(tf), len(tw), mean(tf), mean(tw)))
+    print("| copy of %d MiB (`copyBuffer`) | %d / %d | %.1f | %.1f | | | |" % (
+        copy_bytes >> 20, len(cf), len(cw), statistics.median(cf), statistics.median(cw)))
     print()
+    print("All dispatches include the autotuner's (whole rows, and blocks of rows while it tries row "
+          "splits); timed calls are the dispatches right after bench.py's 1 GiB scratch write.")
     print("Calibration: the copy reads and writes %.0f KiB per dispatch, so FETCH_SIZE is scaled by %.3f and "
           "WRITE_SIZE by %.3f." % (copy_kib, f_scale, w_scale))
     for n in names:
-        f, w = fetch.get(n, []), write.get(n, [])
-        if f and w:
-            b = (statistics.mean(f) * f_scale + statistics.mean(w) * w_scale) * 1024
-            print("`%s`: %.4g bytes per dispatch from HBM-side counters." % (n, b))
+        tf, tw = _after_flush(fseq, n, flush), _after_flush(wseq, n, flush)
+        if tf and tw:
+            b = (statistics.mean(tf) * f_scale + statistics.mean(tw) * w_scale) * 1024
+            print("`%s`: %.4g bytes per timed call from HBM-side counters." % (n, b))
+
+
+def _variant_kernels(def_path):
+    """{variant id: (kernel base name, template arguments after the input
+    type)} from the X-macro variant list, as srs_inst.inc instantiates them."""
+    import re
+    with open(def_path) as f:
+        text = re.sub(r"/\*.*?\*/|//[^\n]*", "", f.read(), flags=re.S)
+    out = {}
+    for m in re.finditer(r"(X_\w+)\(([^)]*)\)", text):
+        kind, args = m.group(1), [a.strip() for a in m.group(2).split(",")]
+        if kind == "X_LDS":
+            out[int(args[0])] = ("srs_lds_kernel", tuple(args[1:4]))
+        elif kind == "X_LDSP":
+            out[int(args[0])] = ("srs_ldsp_kernel", tuple(args[1:6]))
+        elif kind == "X_RW":
+            out[int(args[0])] = ("srs_regwin_kernel", tuple(args[1:7]) + ("1",))
+        elif kind == "X_RWO":
+            out[int(args[0])] = ("srs_regwin_kernel", tuple(args[1:8]))
+        elif kind == "X_DIRECT":
+            rb, v = int(args[4]), int(args[5])
+            out[int(args[0])] = ("srs_direct_kernel", tuple(args[1:4]) + (
+                "true" if rb > 0 else "false", "true" if v else "false"))
+    return out
+
+
+def _kernel_key(name):
+    """(base name, template arguments after the input type) of a kernel name."""
+    import re
+    m = re.search(r"(srs_\w+_kernel)<([^>]*)>", name)
+    if not m:
+        return None
+    args = [a.strip() for a in m.group(2).split(",")]
+    return m.group(1), tuple(args[1:])
+
+
+def traffic(fetch_dir, write_dir, workload, variant, copy_bytes, flush):
+    import json
+    here = os.path.dirname(os.path.abspath(__file__))
+    sys.path.insert(0, here)
+    import bench  # the source hash and variant entries bench.py compares against
+    fetch, write = _counter(fetch_dir, "FETCH_SIZE"), _counter(write_dir, "WRITE_SIZE")
+    copy_kib = copy_bytes / 1024.0
+    cf = [x for k, v in fetch.items() if "copyBuffer" in k for x in v]
+    cw = [x for k, v in write.items() if "copyBuffer" in k for x in v]
+    if not cf or not cw:
+        raise SystemExit("no copyBuffer dispatches to calibrate against")
+    f_scale, w_scale = copy_kib / statistics.median(cf), copy_kib / statistics.median(cw)
+    owners = _owners(here)
+    fseq, wseq = _counter_seq(fetch_dir, "FETCH_SIZE"), _counter_seq(write_dir, "WRITE_SIZE")
+    ftune, wtune = _tuning_runs(fseq, owners), _tuning_runs(wseq, owners)
+    by_variant = {}
+    for name in sorted(set(fetch) & set(write)):
+        key = _kernel_key(name)
+        if key is None or "<float," not in name or len(owners.get(key, [])) != 1:
+            continue
+        vid = owners[key][0]
+        f, w = _after_flush(fseq, name, flush), _after_flush(wseq, name, flush)
+        if not f or not w:
+            f, w = ftune.get(vid), wtune.get(vid)
+        if not f or not w:
+            continue
+        b = (statistics.mean(f) * f_scale + statistics.mean(w) * w_scale) * 1024
+        by_variant[str(vid)] = {"bytes": round(b), "entry": bench.variant_entry(vid)}
+    if str(variant) not in by_variant:
+        raise SystemExit("variant %d did not run in the counter runs" % variant)
+    json.dump({"workload": workload, "variant": variant, "source_hash": bench.kernel_source_hash(),
+               "by_variant": dict(sorted(by_variant.items(), key=lambda kv: int(kv[0])))}, sys.stdout, indent=1)
+    print()
+
+
+def variants(trace_dir, traffic_json):
+    import json
+    owners = _owners(os.path.dirname(os.path.abspath(__file__)))
+    with open(traffic_json) as f:
+        tr = json.load(f).get("by_variant", {})
+    seq = [(n, e - s) for n, s, e in _dispatches(trace_dir)]
+    names = {}
+    for n, _ in seq:
+        key = _kernel_key(n)
+        if key is not None and len(owners.get(key, [])) == 1:
+            names[owners[key][0]] = n
+    print("| variant | kernel | dispatches | average ns | HBM-side bytes per launch |")
+    print("|---|---|---|---|---|")
+    for vid, run in sorted(_tuning_runs(seq, owners).items()):
+        short = names[vid].split("(")[0].replace("void dd::kern::", "")
+        b = tr.get(str(vid), {}).get("bytes")
+        print("| %d | `%s` | %d | %.0f | %s |" % (vid, short, len(run), statistics.mean(run),
+                                                "-" if b is None else "%.3g" % b))
 
 
 KINDS = {0: "LDS", 1: "register window", 2: "direct"}
@@ -215,16 +370,31 @@ def main(argv=None):
     c.add_argument("write_dir")
     c.add_argument("kernel")
     c.add_argument("--copy-bytes", type=int, default=256 << 20)
+    c.add_argument("--calls-after", default="Fill")
+    tr = sub.add_parser("traffic")
+    tr.add_argument("fetch_dir")
+    tr.add_argument("write_dir")
+    tr.add_argument("workload")
+    tr.add_argument("variant", type=int)
+    tr.add_argument("--copy-bytes", type=int, default=256 << 20)
+    tr.add_argument("--calls-after", default="Fill")
+    va = sub.add_parser("variants")
+    va.add_argument("trace_dir")
+    va.add_argument("traffic_json")
     st = sub.add_parser("study")
     st.add_argument("json")
     st.add_argument("--curated", type=int, default=46)
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         trace(a.dir, a.kernel, a.calls_after)
+    elif a.cmd == "traffic":
+        traffic(a.fetch_dir, a.write_dir, a.workload, a.variant, a.copy_bytes, a.calls_after)
+    elif a.cmd == "variants":
+        variants(a.trace_dir, a.traffic_json)
     elif a.cmd == "study":
         study(a.json, a.curated)
     else:
-        counters(a.fetch_dir, a.write_dir, a.kernel, a.copy_bytes)
+        counters(a.fetch_dir, a.write_dir, a.kernel, a.copy_bytes, a.calls_after)
 
 
 if __name__ == "__main__":
