@@ -28,6 +28,11 @@
         of the kernel sources (bench.py uses the bytes only while both match).
         Variants whose kernel name another variant shares are left out.
 
+    python3 profsum.py sq DIR KERNEL [--calls-after FLUSH]
+        Every counter of one rocprofv3 --pmc run (DIR) for the matching
+        kernel: the mean over its timed calls (the dispatches right after the
+        1 GiB scratch write), per dispatch.
+
     python3 profsum.py variants TRACE_DIR TRAFFIC_JSON
         Per tile variant the autotuner timed over all rows in the traced
         program (its first pass, variants in id order): the mean dispatch
@@ -167,19 +172,22 @@ def _owners(here):
     return owners
 
 
+def _copies(tab):
+    """Counter values of the calibration copies: the copyBuffer dispatches of
+    at least half the largest one's count (the program may make small copies
+    too)."""
+    v = [x for k, vals in tab.items() if "copyBuffer" in k for x in vals]
+    if not v:
+        raise SystemExit("no copyBuffer dispatches to calibrate against")
+    return [x for x in v if x >= 0.5 * max(v)]
+
+
 def counters(fetch_dir, write_dir, kernel, copy_bytes, flush):
     fseq, wseq = _counter_seq(fetch_dir, "FETCH_SIZE"), _counter_seq(write_dir, "WRITE_SIZE")
     fetch, write = _counter(fetch_dir, "FETCH_SIZE"), _counter(write_dir, "WRITE_SIZE")
     copy_kib = copy_bytes / 1024.0
 
-    def pick(tab, key):
-        ks = [k for k in tab if key in k]
-        return ks, [x for k in ks for x in tab[k]]
-
-    _, cf = pick(fetch, "copyBuffer")
-    _, cw = pick(write, "copyBuffer")
-    if not cf or not cw:
-        raise SystemExit("no copyBuffer dispatches to calibrate against")
+    cf, cw = _copies(fetch), _copies(write)
     f_scale = copy_kib / statistics.median(cf)
     w_scale = copy_kib / statistics.median(cw)
     names = sorted({k for k in list(fetch) + list(write) if kernel in k})
@@ -205,6 +213,23 @@ def counters(fetch_dir, write_dir, kernel, copy_bytes, flush):
         if tf and tw:
             b = (statistics.mean(tf) * f_scale + statistics.mean(tw) * w_scale) * 1024
             print("`%s`: %.4g bytes per timed call from HBM-side counters." % (n, b))
+
+
+def sq(directory, kernel, flush):
+    names = set()
+    counters = set()
+    for r in _rows(directory, "counter_collection.csv"):
+        counters.add(r["Counter_Name"])
+        if kernel in r["Kernel_Name"]:
+            names.add(r["Kernel_Name"])
+    if len(names) != 1:
+        raise SystemExit("need exactly one kernel matching %r, found %d" % (kernel, len(names)))
+    name = names.pop()
+    print("| counter | timed calls | mean per dispatch |")
+    print("|---|---|---|")
+    for c in sorted(counters):
+        v = _after_flush(_counter_seq(directory, c), name, flush)
+        print("| `%s` | %d | %s |" % (c, len(v), "%.4g" % statistics.mean(v) if v else "-"))
 
 
 def _variant_kernels(def_path):
@@ -248,10 +273,7 @@ def traffic(fetch_dir, write_dir, workload, variant, copy_bytes, flush):
     import bench  # the source hash and variant entries bench.py compares against
     fetch, write = _counter(fetch_dir, "FETCH_SIZE"), _counter(write_dir, "WRITE_SIZE")
     copy_kib = copy_bytes / 1024.0
-    cf = [x for k, v in fetch.items() if "copyBuffer" in k for x in v]
-    cw = [x for k, v in write.items() if "copyBuffer" in k for x in v]
-    if not cf or not cw:
-        raise SystemExit("no copyBuffer dispatches to calibrate against")
+    cf, cw = _copies(fetch), _copies(write)
     f_scale, w_scale = copy_kib / statistics.median(cf), copy_kib / statistics.median(cw)
     owners = _owners(here)
     fseq, wseq = _counter_seq(fetch_dir, "FETCH_SIZE"), _counter_seq(write_dir, "WRITE_SIZE")
@@ -378,6 +400,10 @@ def main(argv=None):
     tr.add_argument("variant", type=int)
     tr.add_argument("--copy-bytes", type=int, default=256 << 20)
     tr.add_argument("--calls-after", default="Fill")
+    q = sub.add_parser("sq")
+    q.add_argument("dir")
+    q.add_argument("kernel")
+    q.add_argument("--calls-after", default="Fill")
     va = sub.add_parser("variants")
     va.add_argument("trace_dir")
     va.add_argument("traffic_json")
@@ -389,6 +415,8 @@ def main(argv=None):
         trace(a.dir, a.kernel, a.calls_after)
     elif a.cmd == "traffic":
         traffic(a.fetch_dir, a.write_dir, a.workload, a.variant, a.copy_bytes, a.calls_after)
+    elif a.cmd == "sq":
+        sq(a.dir, a.kernel, a.calls_after)
     elif a.cmd == "variants":
         variants(a.trace_dir, a.traffic_json)
     elif a.cmd == "study":
