@@ -160,11 +160,12 @@ extern "C" int dd_batch_create(dd_batch **out, const dd_plan *const *plans, int3
         bd.d.n_rows = a.n_rows;
         bd.d.wcap = a.wcap;
         bd.d.rows_per_chunk = a.rows_per_chunk;
-        bd.d.n_t_tiles = static_cast<int32_t>((a.n_t + v->tt() - 1) / v->tt());
+        bd.d.n_t_tiles = a.n_t_tiles > 0 ? a.n_t_tiles : static_cast<int32_t>((a.n_t + v->tt() - 1) / v->tt());
         bd.d.n_acc_tiles = (a.n_acc + v->ta() - 1) / v->ta();
         bd.d.r_begin = 0;
         bd.d.r_end = a.n_rows;
         bd.d.carry = 0;
+        bd.d.skew = a.skew;
         const uint64_t n = static_cast<uint64_t>(bd.d.n_t_tiles) * bd.d.n_acc_tiles;
         if (n >= (1u << 24)) {
             batch_free(B);

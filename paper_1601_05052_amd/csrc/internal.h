@@ -78,6 +78,8 @@ struct SrsArgs {
     int32_t r_begin = 0;   // input rows [r_begin, r_end) summed by this launch
     int32_t r_end = 0;
     int32_t carry = 0;     // 1: continue the partial sums already in out
+    const int32_t *skew = nullptr;  // LDS kinds, regwin: [n_acc] tile skew per accumulator row (null: none)
+    int32_t n_t_tiles = 0;          // time tiles (0: ceil(n_t / tt), the count without skew)
 };
 
 // Element types the kernels read.
@@ -120,7 +122,9 @@ struct Layout {
     int32_t rows_per_chunk = 0;
     int32_t lds_bytes = 0;
     int32_t max_spread = 0;
+    int32_t n_t_tiles = 0;  // time tiles: ceil((n_t + max skew) / tt)
     std::vector<int32_t> base, rel, recs, span;
+    std::vector<int32_t> skew;  // per accumulator row, multiples of 4 samples; empty when all zero
 };
 
 // Device copy of a Layout's tables.
@@ -133,6 +137,8 @@ struct TileTables {
     int32_t *d_rel = nullptr;
     int32_t *d_recs = nullptr;
     int32_t *d_span = nullptr;
+    int32_t *d_skew = nullptr;
+    int32_t n_t_tiles = 0;
 };
 
 int32_t max_lds_bytes();

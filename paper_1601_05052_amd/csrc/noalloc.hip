@@ -98,7 +98,8 @@ extern "C" int dd_dedisperse_noalloc(const dd_plan *p, const void *d_in, dd_dtyp
                         "the plan's forward tables for tile variant %d are not built: call dd_plan_prepare (or "
                         "dd_dedisperse) once beforehand, where allocation is allowed", v->id);
         lays.push_back(L);
-        need += aligned_bytes(L->base) + aligned_bytes(L->rel) + aligned_bytes(L->recs) + aligned_bytes(L->span);
+        need += aligned_bytes(L->base) + aligned_bytes(L->rel) + aligned_bytes(L->recs) + aligned_bytes(L->span) +
+                aligned_bytes(L->skew);
     }
     if (need > kScratchBytes)
         return fail(DD_EUNSUPPORTED, "the tile tables need %zu bytes; the allocation-free entry holds at most %zu",
@@ -121,8 +122,10 @@ extern "C" int dd_dedisperse_noalloc(const dd_plan *p, const void *d_in, dd_dtyp
         if ((rc = stage(L->base, base, &off, stream, &a.base)) != DD_OK ||
             (rc = stage(L->rel, base, &off, stream, &a.rel)) != DD_OK ||
             (rc = stage(L->recs, base, &off, stream, &a.recs)) != DD_OK ||
-            (rc = stage(L->span, base, &off, stream, &a.span)) != DD_OK)
+            (rc = stage(L->span, base, &off, stream, &a.span)) != DD_OK ||
+            (rc = stage(L->skew, base, &off, stream, &a.skew)) != DD_OK)
             return rc;
+        a.n_t_tiles = L->n_t_tiles;
         a.wcap = L->wcap;
         a.rows_per_chunk = L->rows_per_chunk;
         a.lds_bytes = L->lds_bytes;

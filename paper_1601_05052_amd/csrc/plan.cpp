@@ -88,6 +88,39 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
     const int32_t cr = v.kind == KIND_LDS && v.kmax == 0 ? 1 : v.waves * std::max(1, v.rpw);
     if (r0 < 0 || r1 > R || r0 >= r1 || r0 % cr != 0 || (v.kind == KIND_DIRECT && (r0 != 0 || r1 != R)))
         return;
+    // Skewed tiles (staged kinds): within an accumulator tile, row a's tiles
+    // start skew[a] samples later, skew[a] being the offset of row a from the
+    // tile's first row averaged over the block's first and last input rows
+    // (the delays are a product of a DM and a channel term, monotone in both,
+    // so these rows bound the offset differences), rounded down to a multiple
+    // of 4 samples.  The tables then hold O[r][a] - skew[a]: their spread
+    // across a tile shrinks from the widest row's to half the change over
+    // the block, and the kernels store tile sample tau at tau - skew[a].
+    std::vector<int32_t> sk;
+    int32_t max_skew = 0;
+    if (block_capable(v)) {
+        sk.assign(A, 0);
+        for (int32_t k = 0; k < n_tiles; ++k) {
+            const int32_t a0 = k * TA, a1 = std::min(A, a0 + TA);
+            int64_t lo = std::numeric_limits<int64_t>::max();
+            std::vector<int64_t> raw(a1 - a0);
+            for (int32_t a = a0; a < a1; ++a) {
+                const int64_t d0 = (int64_t)offset_of(p, direction, r0, a) - offset_of(p, direction, r0, a0);
+                const int64_t d1 = (int64_t)offset_of(p, direction, r1 - 1, a) - offset_of(p, direction, r1 - 1, a0);
+                const int64_t sum = d0 + d1;
+                raw[a - a0] = sum >= 0 ? sum / 2 : -((-sum + 1) / 2);  // floor((d0 + d1) / 2)
+                lo = std::min(lo, raw[a - a0]);
+            }
+            for (int32_t a = a0; a < a1; ++a) {
+                sk[a] = static_cast<int32_t>((raw[a - a0] - lo) / 4 * 4);
+                max_skew = std::max(max_skew, sk[a]);
+            }
+        }
+        if (max_skew == 0)
+            sk.clear();
+    }
+    // Offsets as the tables hold them.
+    auto off = [&](int32_t r, int32_t a) { return offset_of(p, direction, r, a) - (sk.empty() ? 0 : sk[a]); };
     if (build) {
         L->base.resize((size_t)n_tiles * Rb);
         if (v.kind != KIND_REGWIN)
@@ -106,7 +139,8 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
     const bool want_span = build && (v.kind == KIND_REGWIN || v.kind == KIND_DIRECT);
     const int64_t n_t = direction == DD_FORWARD ? p->S : p->T_in;
     const int64_t in_valid = direction == DD_FORWARD ? p->T_in : p->S;
-    const int32_t n_t_tiles = static_cast<int32_t>((n_t + TT - 1) / TT);
+    const int32_t n_t_tiles = static_cast<int32_t>((n_t + max_skew + TT - 1) / TT);
+    L->n_t_tiles = n_t_tiles;
     std::vector<int32_t> row_lo, row_hi;
     if (want_span) {
         L->span.assign(static_cast<size_t>(n_tiles) * n_t_tiles * 2, 0);
@@ -117,7 +151,7 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
         for (int32_t r = 0; r < R && ok; ++r) {
             int32_t lo = std::numeric_limits<int32_t>::max(), hi = std::numeric_limits<int32_t>::min();
             for (int32_t j = 0; j < TA; ++j) {
-                const int32_t o = offset_of(p, direction, r, std::min(A - 1, k * TA + j));  // ragged tile repeats its last row
+                const int32_t o = off(r, std::min(A - 1, k * TA + j));  // ragged tile repeats its last row
                 lo = std::min(lo, o);
                 hi = std::max(hi, o);
             }
@@ -139,7 +173,7 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
             if (v.kind != KIND_REGWIN) {
                 if (build)
                     for (int32_t j = 0; j < TA; ++j)
-                        L->rel[((size_t)k * Rb + rb) * TA + j] = offset_of(p, direction, r, std::min(A - 1, k * TA + j)) - lo;
+                        L->rel[((size_t)k * Rb + rb) * TA + j] = off(r, std::min(A - 1, k * TA + j)) - lo;
                 continue;
             }
             const int32_t TDW = v.items_acc;
@@ -148,7 +182,7 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
             for (int32_t w = 0; w < v.waves; ++w) {
                 int32_t wmin = std::numeric_limits<int32_t>::max(), wmax = 0;
                 for (int32_t j = 0; j < TDW; ++j) {
-                    const int32_t o = offset_of(p, direction, r, std::min(A - 1, k * TA + w * TDW + j)) - b;
+                    const int32_t o = off(r, std::min(A - 1, k * TA + w * TDW + j)) - b;
                     wmin = std::min(wmin, o);
                     wmax = std::max(wmax, o);
                 }
@@ -169,7 +203,7 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
                     int32_t *rec = &L->recs[(((size_t)k * v.waves + w) * regwin_rows(v, Rb) + rb) * RD];
                     rec[0] = u_bytes | (nq << 20);
                     for (int32_t j = 0; j < TDW; ++j) {
-                        const uint32_t o = (uint32_t)(offset_of(p, direction, r, std::min(A - 1, k * TA + w * TDW + j)) -
+                        const uint32_t o = (uint32_t)(off(r, std::min(A - 1, k * TA + w * TDW + j)) -
                                                       b - ws);  // 0 <= o <= nwr - items_t < 256
                         rec[1 + j / 4] = (int32_t)((uint32_t)rec[1 + j / 4] | (o << (8 * (j % 4))));
                     }
@@ -179,7 +213,7 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
         if (want_span && ok) {
             for (int32_t j = 0; j < n_t_tiles; ++j) {
                 const int64_t t_first = static_cast<int64_t>(j) * TT;
-                const int64_t t_last = std::min<int64_t>(n_t, t_first + TT) - 1;
+                const int64_t t_last = std::min<int64_t>(n_t + max_skew, t_first + TT) - 1;
                 int32_t first = R, last = -1;
                 for (int32_t r = 0; r < R; ++r) {
                     if (t_first + row_lo[r] <= in_valid - 1 && t_last + row_hi[r] >= 0) {
@@ -196,6 +230,8 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
     L->max_spread = max_spread;
     if (!ok)
         return;
+    if (build)
+        L->skew = sk;
     // Spans that skip nothing (every forward plan: the input covers every
     // operand) are dropped; the kernels then take all rows.
     bool skips = false;
@@ -284,6 +320,7 @@ static void free_tables(TileTables &t) {
     (void)hipFree(t.d_rel);
     (void)hipFree(t.d_recs);
     (void)hipFree(t.d_span);
+    (void)hipFree(t.d_skew);
     t = TileTables();
 }
 
@@ -316,6 +353,7 @@ int plan_tables(const dd_plan *p, int direction, const Variant &v, const TileTab
     t.wcap = L.wcap;
     t.rows_per_chunk = L.rows_per_chunk;
     t.lds_bytes = L.lds_bytes;
+    t.n_t_tiles = L.n_t_tiles;
     int rc = upload(L.base, &t.d_base);
     if (rc == DD_OK)
         rc = upload(L.rel, &t.d_rel);
@@ -323,6 +361,8 @@ int plan_tables(const dd_plan *p, int direction, const Variant &v, const TileTab
         rc = upload(L.recs, &t.d_recs);
     if (rc == DD_OK)
         rc = upload(L.span, &t.d_span);
+    if (rc == DD_OK)
+        rc = upload(L.skew, &t.d_skew);
     if (rc != DD_OK) {
         free_tables(t);
         return rc;
@@ -407,6 +447,8 @@ int make_args(const dd_plan *p, int direction, const Variant &v, const void *in,
     a->base = t->d_base;
     a->recs = t->d_recs;
     a->span = t->d_span;
+    a->skew = t->d_skew;
+    a->n_t_tiles = t->n_t_tiles;
     a->wcap = t->wcap;
     a->rows_per_chunk = t->rows_per_chunk;
     a->lds_bytes = t->lds_bytes;

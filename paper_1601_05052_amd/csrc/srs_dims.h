@@ -24,6 +24,11 @@ struct SrsDims {
     int32_t r_begin;
     int32_t r_end;
     int32_t carry;
+    // Per accumulator row, the skew of its tiles (null: none): a tile's
+    // sample tau holds output sample tau - skew[a] of row a, so every
+    // accumulator row of a tile can follow the delay curve and the rows'
+    // windows line up.  The tables hold offsets O[r][a] - skew[a].
+    const int32_t *skew;
 };
 
 }  // namespace dev

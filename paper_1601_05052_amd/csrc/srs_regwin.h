@@ -243,15 +243,15 @@ struct ChunkStager {
 template <typename RW, int IT, int TDW, int TA>
 __device__ __forceinline__ void store_acc(const typename RW::Acc &acc, float *__restrict__ out, const SrsDims &d,
                                           int64_t t0, int32_t tile_a, int wave, int lane) {
-    const int64_t tl = t0 + static_cast<int64_t>(lane) * IT;
 #pragma unroll
     for (int a = 0; a < TDW; ++a) {
         const int32_t ag = tile_a * TA + wave * TDW + a;
         if (ag >= d.n_acc)
             break;
+        const int64_t tl = t0 - skew_of(d, ag) + static_cast<int64_t>(lane) * IT;
         float *dst = out + static_cast<int64_t>(ag) * d.out_stride + tl;
         const bool vec = (reinterpret_cast<uintptr_t>(dst) & 15) == 0;
-        if (tl + IT <= d.n_t && vec) {
+        if (tl >= 0 && tl + IT <= d.n_t && vec) {
 #pragma unroll
             for (int j = 0; j < IT; j += 4) {
                 v4f v;
@@ -264,7 +264,7 @@ __device__ __forceinline__ void store_acc(const typename RW::Acc &acc, float *__
         } else {
 #pragma unroll
             for (int j = 0; j < IT; ++j)
-                if (tl + j < d.n_t)
+                if (tl + j >= 0 && tl + j < d.n_t)
                     dst[j] = RW::get_acc(acc, a * IT + j);
         }
     }
@@ -312,15 +312,15 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
     for (int i = 0; i < IT * TDW; ++i)
         RW::set_acc(acc, i, 0.f);
     if (d.carry) {  // continue the partial sums of the previous blocks
-        const int64_t tl = t0 + static_cast<int64_t>(lane) * IT;
 #pragma unroll
         for (int a = 0; a < TDW; ++a) {
             const int32_t ag = tile_a * TA + wave * TDW + a;
             if (ag < d.n_acc) {
+                const int64_t tl = t0 - skew_of(d, ag) + static_cast<int64_t>(lane) * IT;
                 const float *src = out + static_cast<int64_t>(ag) * d.out_stride + tl;
 #pragma unroll
                 for (int j = 0; j < IT; ++j)
-                    if (tl + j < d.n_t)
+                    if (tl + j >= 0 && tl + j < d.n_t)
                         RW::set_acc(acc, a * IT + j, src[j]);
             }
         }
@@ -420,11 +420,13 @@ __device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float 
 #pragma unroll
     for (int k = 0; k < TDW; ++k) {
         const int32_t ag = tile_a * TA + wave * TDW + k;
+        const int64_t ts = t0 - skew_of(d, ag);  // output sample of this row's tile sample t0
 #pragma unroll
         for (int j = 0; j < IT; ++j) {
-            const int64_t t = t0 + lane + 64 * j;
+            const int64_t t = ts + lane + 64 * j;
             // carry: continue the partial sums of the previous blocks of rows
-            acc[k][j] = d.carry && ag < d.n_acc && t < d.n_t ? out[static_cast<int64_t>(ag) * d.out_stride + t] : 0.f;
+            acc[k][j] = d.carry && ag < d.n_acc && t >= 0 && t < d.n_t ? out[static_cast<int64_t>(ag) * d.out_stride + t]
+                                                                       : 0.f;
         }
     }
 
@@ -551,10 +553,11 @@ __device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float 
         const int32_t ag = tile_a * TA + wave * TDW + k;
         if (ag < d.n_acc) {
             float *dst = out + static_cast<int64_t>(ag) * d.out_stride;
+            const int64_t ts = t0 - skew_of(d, ag);
 #pragma unroll
             for (int j = 0; j < IT; ++j) {
-                const int64_t t = t0 + lane + 64 * j;
-                if (t < d.n_t)
+                const int64_t t = ts + lane + 64 * j;
+                if (t >= 0 && t < d.n_t)
                     __builtin_nontemporal_store(acc[k][j], dst + t);
             }
         }

@@ -29,6 +29,12 @@ __device__ __forceinline__ float to_f32<uint8_t>(uint8_t v) { return static_cast
 typedef const __attribute__((address_space(4))) int32_t ctab;
 __device__ __forceinline__ ctab *as_ctab(const int32_t *p) { return (ctab *)reinterpret_cast<uintptr_t>(p); }
 
+// Tile skew of accumulator row ag: its tile sample tau is output sample
+// tau - skew (0 without skew tables or past the last row).
+__device__ __forceinline__ int32_t skew_of(const SrsDims &d, int32_t ag) {
+    return d.skew && ag < d.n_acc ? __builtin_amdgcn_readfirstlane(as_ctab(d.skew)[ag]) : 0;
+}
+
 
 // Map the hardware work-group id to (time tile, accumulator tile).  Work-groups
 // are dealt round-robin to the 8 XCDs; renumber so that each XCD receives a
@@ -68,11 +74,13 @@ __device__ __forceinline__ void srs_tile_lds(const TIn *__restrict__ in, float *
 #pragma unroll
     for (int k = 0; k < TDW; ++k) {
         const int32_t ag = tile_a * TA + wave * TDW + k;
+        const int64_t ts = t0 - skew_of(d, ag);  // output sample of this row's tile sample t0
 #pragma unroll
         for (int j = 0; j < IT; ++j) {
-            const int64_t t = t0 + lane + 64 * j;
+            const int64_t t = ts + lane + 64 * j;
             // carry: continue the partial sums of the previous blocks of rows
-            acc[k][j] = d.carry && ag < d.n_acc && t < d.n_t ? out[static_cast<int64_t>(ag) * d.out_stride + t] : 0.f;
+            acc[k][j] = d.carry && ag < d.n_acc && t >= 0 && t < d.n_t ? out[static_cast<int64_t>(ag) * d.out_stride + t]
+                                                                       : 0.f;
         }
     }
 
@@ -112,10 +120,11 @@ __device__ __forceinline__ void srs_tile_lds(const TIn *__restrict__ in, float *
         const int32_t ag = tile_a * TA + wave * TDW + k;
         if (ag < d.n_acc) {
             float *dst = out + static_cast<int64_t>(ag) * d.out_stride;
+            const int64_t ts = t0 - skew_of(d, ag);
 #pragma unroll
             for (int j = 0; j < IT; ++j) {
-                const int64_t t = t0 + lane + 64 * j;
-                if (t < d.n_t)
+                const int64_t t = ts + lane + 64 * j;
+                if (t >= 0 && t < d.n_t)
                     __builtin_nontemporal_store(acc[k][j], dst + t);
             }
         }

@@ -118,7 +118,8 @@ hipError_t launch_srs(const Variant &v, int32_t in_type, const SrsArgs &a, hipSt
     d.r_begin = a.r_begin;
     d.r_end = a.r_end;
     d.carry = a.carry;
-    d.n_t_tiles = static_cast<int32_t>((a.n_t + v.tt() - 1) / v.tt());
+    d.skew = a.skew;
+    d.n_t_tiles = a.n_t_tiles > 0 ? a.n_t_tiles : static_cast<int32_t>((a.n_t + v.tt() - 1) / v.tt());
     d.n_acc_tiles = (a.n_acc + v.ta() - 1) / v.ta();
     const uint64_t blocks = static_cast<uint64_t>(d.n_t_tiles) * d.n_acc_tiles;
     if (blocks == 0)
