@@ -89,6 +89,12 @@ def measured_traffic(workload, variant):
     return rec.get("bytes")
 
 
+def vdesc(r):
+    """The tile variant of a measurement, or its row split [(first row, variant)]."""
+    b = r.get("blocks") or []
+    return "variant %d" % r["tile"] if len(b) <= 1 else "row blocks %s" % b
+
+
 def compulsory_bytes(setup, in_bytes_per_sample, plan):
     """Each input sample read once, each output written once (Eq. (3)'s
     reuse limit), plus the delay table."""
@@ -173,7 +179,8 @@ def measure_forward(torch, dd, setup, dtype, steps, warmup, stream, numpy_input=
     t = timed_protocol(torch, lambda: dd.dedisperse(x, plan, out=out), steps, warmup, stream)
     bpe = {"f32": 4, "f16": 2, "u8": 1}[dtype]
     return dict(t, gflops=setup.adds / (t["ms"] * 1e-3) / 1e9,
-                compulsory_bytes=compulsory_bytes(setup, bpe, plan), tile=plan.get_tile(dtype=code)), plan
+                compulsory_bytes=compulsory_bytes(setup, bpe, plan), tile=plan.get_tile(dtype=code),
+                blocks=plan.get_blocks(dtype=code)), plan
 
 
 def measure_adjoint(torch, dd, setup, steps, warmup, stream):
@@ -187,7 +194,8 @@ def measure_adjoint(torch, dd, setup, steps, warmup, stream):
     gx = torch.empty((setup.n_channels, plan.input_samples), device="cuda")
     t = timed_protocol(torch, lambda: dd.dedisperse_adjoint(gy, plan, out=gx), steps, warmup, stream)
     return dict(t, gflops=setup.adds / (t["ms"] * 1e-3) / 1e9,
-                compulsory_bytes=compulsory_bytes(setup, 4, plan), tile=plan.get_tile(direction=dd.DD_ADJOINT))
+                compulsory_bytes=compulsory_bytes(setup, 4, plan), tile=plan.get_tile(direction=dd.DD_ADJOINT),
+                blocks=plan.get_blocks(direction=dd.DD_ADJOINT))
 
 
 def cpu_baseline(setup, budget_s=12.0):
@@ -287,24 +295,24 @@ def extras(torch, dd, stream, steps, only=None):
         r, _ = measure_forward(torch, dd, synth.LOFAR, "f32", steps, 2, stream)
         r["hbm_GBps"] = r["compulsory_bytes"] / (r["ms"] * 1e-3) / 1e9
         res["lofar_f32"] = r
-        log("lofar f32: %.3f ms %.1f GFLOP/s (variant %d)" % (r["ms"], r["gflops"], r["tile"]))
+        log("lofar f32: %.3f ms %.1f GFLOP/s (%s)" % (r["ms"], r["gflops"], vdesc(r)))
     if want("lofar_adjoint"):
         r = measure_adjoint(torch, dd, synth.LOFAR, steps, 2, stream)
         res["lofar_adjoint"] = r
-        log("lofar adjoint: %.3f ms (variant %d)" % (r["ms"], r["tile"]))
+        log("lofar adjoint: %.3f ms (%s)" % (r["ms"], vdesc(r)))
     # low precision storage, Apertif
     for dt in ("u8", "f16"):
         if want("apertif_" + dt):
             r, _ = measure_forward(torch, dd, synth.APERTIF, dt, steps, 2, stream)
             res["apertif_" + dt] = r
-            log("apertif %s: %.3f ms %.1f GFLOP/s (variant %d)" % (dt, r["ms"], r["gflops"], r["tile"]))
+            log("apertif %s: %.3f ms %.1f GFLOP/s (%s)" % (dt, r["ms"], r["gflops"], vdesc(r)))
     # perfect-reuse limit (Sec. IV-C / V-C): every trial DM is 0, tuned again
     for base in (synth.APERTIF, synth.LOFAR):
         z = dataclasses.replace(base, name=base.name + "_0dm", dm_step=0.0)
         if want(z.name):
             r, _ = measure_forward(torch, dd, z, "f32", steps, 2, stream)
             res[z.name] = r
-            log("%s: %.3f ms %.1f GFLOP/s (variant %d)" % (z.name, r["ms"], r["gflops"], r["tile"]))
+            log("%s: %.3f ms %.1f GFLOP/s (%s)" % (z.name, r["ms"], r["gflops"], vdesc(r)))
     # candidate search over the dedispersed Apertif rows (boxcars of 1 .. 1,024 samples)
     if want("search_apertif"):
         sp = dd.Plan.from_setup(synth.APERTIF)
@@ -369,9 +377,10 @@ def fwd_bwd(torch, dd, stream, steps, want):
         t = timed_protocol(torch, lambda: dd.dedisperse_adjoint(gy, plans[0], out=gx0), steps, 2, stream)
         ms_adj = t["ms"]
         res["apertif_adjoint"] = dict(t, gflops=beams[0].adds / (ms_adj * 1e-3) / 1e9,
-                                      tile=plans[0].get_tile(direction=dd.DD_ADJOINT))
+                                      tile=plans[0].get_tile(direction=dd.DD_ADJOINT),
+                                      blocks=plans[0].get_blocks(direction=dd.DD_ADJOINT))
         del gx0, gy
-        log("apertif adjoint: %.3f ms (variant %d)" % (ms_adj, res["apertif_adjoint"]["tile"]))
+        log("apertif adjoint: %.3f ms (%s)" % (ms_adj, vdesc(res["apertif_adjoint"])))
     if not want("fwd_bwd_8beams"):
         return res
     xs = [gpu_input(torch, b, p.input_samples, "f32", b.seed).requires_grad_(True) for b, p in zip(beams, plans)]
@@ -503,8 +512,8 @@ def main():
     else:
         r, plan = measure_forward(torch, dd, setup, "f32", args.steps, args.warmup, stream, numpy_input=x)
     ms = r["ms"]
-    log("%s f32: %.4f ms/step, %.1f GFLOP/s, tile %d" % ("adjoint" if args.adjoint else "forward", ms, r["gflops"],
-                                                          r["tile"]))
+    log("%s f32: %.4f ms/step, %.1f GFLOP/s, %s" % ("adjoint" if args.adjoint else "forward", ms, r["gflops"],
+                                                     vdesc(r)))
     achieved_tflops = setup.adds / (ms * 1e-3) / 1e12
     hbm_gbps = r["compulsory_bytes"] / (ms * 1e-3) / 1e9
     line = {
@@ -527,10 +536,11 @@ def main():
                                    setup.f_min + setup.n_channels * setup.df, round(1 / setup.t_samp),
                                    setup.n_samples, setup.n_dm, setup.dm_first,
                                    setup.dm_first + (setup.n_dm - 1) * setup.dm_step, setup.dm_step),
-                   "tile_variant": r["tile"]},
+                   "tile_variant": r["tile"], "row_blocks": r["blocks"]},
         "roofline": {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": round(ADD_PEAK_TFLOPS, 1),
                      "unit": "TFLOP/s", "frac": round(achieved_tflops / ADD_PEAK_TFLOPS, 4),
-                     "traffic": None if args.adjoint else measured_traffic(setup.name, r["tile"])},
+                     "traffic": None if args.adjoint or len(r["blocks"]) > 1 else measured_traffic(setup.name,
+                                                                                                    r["tile"])},
         "hbm": {"compulsory_bytes": r["compulsory_bytes"], "achieved_GBps": round(hbm_gbps, 1),
                 "peak_GBps": HBM_PEAK_GBPS, "frac": round(hbm_gbps / HBM_PEAK_GBPS, 4)},
         "paper_context": {"hd7970_2000dms_s": 0.106, "hd7970_GFLOPs": round(2000 * 1024 * 20000 / 0.106 / 1e9, 1),

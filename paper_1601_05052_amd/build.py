@@ -2,6 +2,7 @@
 
     python -m paper_1601_05052_amd.build [-v]
     python -m paper_1601_05052_amd.build --study [-v]   # auto-tuning study library
+    python -m paper_1601_05052_amd.build --ceilings     # in-core ceilings microbenchmark
 
 Flags:
   --offload-arch=gfx950        CDNA4 only; no other targets, no CUDA path
@@ -123,6 +124,21 @@ def build_study(verbose: bool = False, jobs: int = 8) -> str:
     return lib
 
 
+def ceilings_path() -> str:
+    return os.path.join(PKG, "ceilings")
+
+
+def build_ceilings() -> str:
+    """The in-core ceilings microbenchmark (ceilings.hip), an executable."""
+    exe = ceilings_path()
+    tmp = exe + ".tmp"
+    proc = subprocess.Popen([hipcc()] + compile_flags() + ["-o", tmp, os.path.join(PKG, "ceilings.hip")],
+                            stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
+    _wait((exe, proc), False)
+    os.replace(tmp, exe)
+    return exe
+
+
 def _wait(item, verbose):
     src, proc = item
     out, _ = proc.communicate()
@@ -139,5 +155,7 @@ def _wait(item, verbose):
 if __name__ == "__main__":
     if "--study" in sys.argv:
         print(build_study(verbose="-v" in sys.argv))
+    elif "--ceilings" in sys.argv:
+        print(build_ceilings())
     else:
         print(build(verbose="-v" in sys.argv))
