@@ -71,7 +71,7 @@ struct SrsArgs {
     const int32_t *rel;    // LDS kind: [n_tiles][n_rows][TA] offsets relative to base
     const int32_t *base;   // [n_tiles][n_rows] staged-row start relative to the tile's first sample
     const int32_t *recs;   // regwin: [n_tiles][waves][n_chunks * rows per chunk][1 + items_acc/4] window records
-    const int32_t *span;   // regwin, direct: [n_tiles][n_t_tiles][2] rows [lo, hi) with an operand in range
+    const int32_t *span;   // regwin, direct, LDS prefetched: [n_tiles][n_t_tiles][2] rows [lo, hi) with an operand in range
     int32_t wcap;          // samples per staged row
     int32_t rows_per_chunk;
     int32_t lds_bytes;     // dynamic LDS per work-group

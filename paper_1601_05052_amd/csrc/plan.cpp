@@ -136,7 +136,8 @@ void compute_layout(const dd_plan *p, int direction, const Variant &v, bool buil
     // least one operand index t + O[r][a] inside [0, in_valid); the others add
     // only zeros there.  Rows are kept when the hull of their operand indices
     // meets the input, so the span is conservative.
-    const bool want_span = build && (v.kind == KIND_REGWIN || v.kind == KIND_DIRECT);
+    const bool want_span =
+        build && (v.kind == KIND_REGWIN || v.kind == KIND_DIRECT || (v.kind == KIND_LDS && v.kmax > 0));
     const int64_t n_t = direction == DD_FORWARD ? p->S : p->T_in;
     const int64_t in_valid = direction == DD_FORWARD ? p->T_in : p->S;
     const int32_t n_t_tiles = static_cast<int32_t>((n_t + max_skew + TT - 1) / TT);

@@ -53,12 +53,12 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(OC
 template <typename TIn, int IT, int TDW, int NW, int RPW, int KMAX>
 __global__ void __launch_bounds__(64 * NW)
     srs_ldsp_kernel(const TIn *__restrict__ in, float *__restrict__ out, const int32_t *__restrict__ rel,
-                    const int32_t *__restrict__ base, SrsDims d) {
+                    const int32_t *__restrict__ base, const int32_t *__restrict__ span, SrsDims d) {
     extern __shared__ __attribute__((aligned(16))) float lds_p[];
     int32_t tile_t, tile_a;
     dev::tile_of_block(d, tile_t, tile_a);
-    dev::srs_tile_ldsp<TIn, IT, TDW, NW, RPW, KMAX>(in, out, dev::as_ctab(rel), dev::as_ctab(base), d, tile_t, tile_a,
-                                                    lds_p);
+    dev::srs_tile_ldsp<TIn, IT, TDW, NW, RPW, KMAX>(in, out, dev::as_ctab(rel), dev::as_ctab(base), dev::as_ctab(span),
+                                                    d, tile_t, tile_a, lds_p);
 }
 
 // VEC: consecutive ownership with 16-byte loads (float32 input only; other
@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(64 * NW)
     if (!beam_tile(ptrs, descs, items, bt))
         return;
     dev::srs_tile_ldsp<TIn, IT, TDW, NW, RPW, KMAX>(static_cast<const TIn *>(bt.in), bt.out, bt.rel,
-                                                    bt.base, bt.d, bt.tile_t, bt.tile_a, lds_mp);
+                                                    bt.base, nullptr, bt.d, bt.tile_t, bt.tile_a, lds_mp);
 }
 
 template <typename TIn, int IT, int NW, int U>
@@ -209,7 +209,7 @@ hipError_t launch_ldsp(const SrsArgs &a, const SrsDims &d, uint32_t blocks, size
     if (e != hipSuccess)
         return e;
     hipLaunchKernelGGL(fn, dim3(blocks), dim3(64 * NW), lds, s, static_cast<const TIn *>(a.in), a.out, a.rel,
-                       a.base, d);
+                       a.base, a.span, d);
     return hipGetLastError();
 }
 

@@ -401,8 +401,8 @@ __device__ __forceinline__ void srs_tile_regwin(const TIn *__restrict__ in, floa
 // operand from LDS at a wave-uniform offset, 64 consecutive words per read).
 template <typename TIn, int IT, int TDW, int NW, int RPW, int KMAX>
 __device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float *__restrict__ out,
-                                              ctab *__restrict__ rel, ctab *__restrict__ base, const SrsDims &d,
-                                              int32_t tile_t, int32_t tile_a, float *lds) {
+                                              ctab *__restrict__ rel, ctab *__restrict__ base, ctab *span,
+                                              const SrsDims &d, int32_t tile_t, int32_t tile_a, float *lds) {
     constexpr int TT = 64 * IT;
     constexpr int TA = TDW * NW;
     constexpr int CR = NW * RPW;
@@ -493,17 +493,28 @@ __device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float 
         }
     };
 
-    fetch_chunk(c_first);
-    store_chunk(c_first);
-    if (c_first + 1 < n_chunks)
-        fetch_chunk(c_first + 1);
+    // Chunks [c_lo, c_hi): with a span, only those holding rows with an
+    // operand inside the input for this tile (the rest would add only zeros;
+    // span: null = all rows).
+    int32_t c_lo = c_first, c_hi = n_chunks;
+    if (span) {
+        const int64_t k = 2 * (static_cast<int64_t>(tile_a) * d.n_t_tiles + tile_t);
+        c_lo = max(c_lo, __builtin_amdgcn_readfirstlane(span[k]) / CR);
+        c_hi = min(c_hi, (__builtin_amdgcn_readfirstlane(span[k + 1]) + CR - 1) / CR);
+    }
+
+    if (c_lo < c_hi) {  // uniform over the work-group
+    fetch_chunk(c_lo);
+    store_chunk(c_lo);
+    if (c_lo + 1 < c_hi)
+        fetch_chunk(c_lo + 1);
     if constexpr (PREF) {
-        load_offsets(onxt, c_first);
-        if (c_first + 1 < n_chunks)
-            load_offsets(onxt2, c_first + 1);
+        load_offsets(onxt, c_lo);
+        if (c_lo + 1 < c_hi)
+            load_offsets(onxt2, c_lo + 1);
     }
     __syncthreads();
-    for (int32_t c = c_first; c < n_chunks; ++c) {
+    for (int32_t c = c_lo; c < c_hi; ++c) {
         const int32_t r0 = c * CR;
         const int32_t nr = min(CR, d.r_end - r0);
         const float *buf = lds + (c & 1) * buf_dw + lane;
@@ -532,9 +543,9 @@ __device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float 
                     acc[k][j] += p[64 * j];
             }
         }
-        if (c + 1 < n_chunks) {
+        if (c + 1 < c_hi) {
             store_chunk(c + 1);
-            if (c + 2 < n_chunks) {
+            if (c + 2 < c_hi) {
                 // Chunk c+2's offsets go out just ahead of its staging loads;
                 // they are used after that staging data has been stored, so
                 // waiting for them never waits on newer loads.
@@ -546,6 +557,7 @@ __device__ __forceinline__ void srs_tile_ldsp(const TIn *__restrict__ in, float 
             }
             __syncthreads();
         }
+    }
     }
 
 #pragma unroll

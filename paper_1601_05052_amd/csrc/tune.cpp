@@ -129,12 +129,17 @@ static int time_blocks(const dd_plan *p, int direction, int32_t in_t, const std:
 
 // Row splits tried by the tuner: the rows cut into 2, 3 or 4 blocks of about
 // equal size at multiples of 64 rows (a multiple of every variant's rows per
-// chunk); every block is timed alone with every variant that can serve it.
-static std::vector<std::vector<int32_t>> split_candidates(int32_t R) {
+// chunk), at least 64 rows each; every block is timed alone with every
+// variant that can serve it.  With `fine` also 8 and 16 blocks: where only
+// the direct kind serves all rows at once (no staged window fits), short
+// blocks can bring the skewed tiles' window within a staged kind's reach.
+static std::vector<std::vector<int32_t>> split_candidates(int32_t R, bool fine) {
     std::vector<std::vector<int32_t>> out;
     if (R < 256)
         return out;
-    for (int32_t nb = 2; nb <= 4; ++nb) {
+    for (int32_t nb : {2, 3, 4, 8, 16}) {
+        if (R / nb < 64 || (nb > 4 && !fine))
+            break;
         std::vector<int32_t> starts{0};
         for (int32_t k = 1; k < nb; ++k) {
             const int32_t r = static_cast<int32_t>(static_cast<int64_t>(R) * k / nb) / 64 * 64;
@@ -205,7 +210,8 @@ int tune_candidates(const dd_plan *p, int direction, int32_t in_type, int32_t re
         // replaces the single variant only if it is faster by more than 2%.
         const int32_t R = plan_rows(p, direction);
         float split_t = 0.98f * best_t;
-        for (const std::vector<int32_t> &starts : split_candidates(R)) {
+        const bool fine = find_variant(best)->kind == KIND_DIRECT;
+        for (const std::vector<int32_t> &starts : split_candidates(R, fine)) {
             std::vector<Block> blocks;
             float total = 0.f;
             for (size_t b = 0; b < starts.size() && rc == DD_OK; ++b) {

@@ -31,7 +31,7 @@
     python3 profsum.py sq DIR KERNEL [--calls-after FLUSH]
         Every counter of one rocprofv3 --pmc run (DIR) for the matching
         kernel: the mean over its timed calls (the dispatches right after the
-        1 GiB scratch write), per dispatch.
+        1 GiB scratch write), per call (summed over a call's dispatches).
 
     python3 profsum.py variants TRACE_DIR TRAFFIC_JSON
         Per tile variant the autotuner timed over all rows in the traced
@@ -139,9 +139,22 @@ def _counter(directory, name):
 
 
 def _after_flush(seq, kernel, flush):
-    """Values of the dispatches of `kernel` that directly follow a dispatch
-    whose name contains `flush` (bench.py's timed calls)."""
-    return [v for (pk, _), (k, v) in zip(seq, seq[1:]) if k == kernel and flush in pk]
+    """Per timed call, the sum over the run of dispatches of `kernel` that
+    directly follows a dispatch whose name contains `flush` (bench.py's timed
+    calls; a call on a row split makes one dispatch per block)."""
+    out, cur, prev_flush = [], None, False
+    for k, v in seq:
+        if k == kernel:
+            if prev_flush:
+                cur = [v]
+                out.append(cur)
+            elif cur is not None:
+                cur.append(v)
+            prev_flush = False
+        else:
+            cur = None
+            prev_flush = flush in k
+    return [sum(c) for c in out]
 
 
 def _tuning_runs(seq, owners):
@@ -193,7 +206,8 @@ def counters(fetch_dir, write_dir, kernel, copy_bytes, flush):
     names = sorted({k for k in list(fetch) + list(write) if kernel in k})
     if not names:
         raise SystemExit("no kernel matching %r" % kernel)
-    print("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | timed calls | FETCH_SIZE KiB | WRITE_SIZE KiB |")
+    print("| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | timed calls | FETCH_SIZE KiB per call "
+          "| WRITE_SIZE KiB per call |")
     print("|---|---|---|---|---|---|---|")
     mean = lambda v: statistics.mean(v) if v else float("nan")  # noqa: E731
     for n in names:
@@ -225,7 +239,7 @@ def sq(directory, kernel, flush):
     if len(names) != 1:
         raise SystemExit("need exactly one kernel matching %r, found %d" % (kernel, len(names)))
     name = names.pop()
-    print("| counter | timed calls | mean per dispatch |")
+    print("| counter | timed calls | mean per call |")
     print("|---|---|---|")
     for c in sorted(counters):
         v = _after_flush(_counter_seq(directory, c), name, flush)
