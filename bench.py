@@ -164,7 +164,7 @@ def gpu_input(torch, setup, T, dtype, seed):
     return torch.clamp(torch.round(z * 16 + 128), 0, 255).to(torch.uint8)
 
 
-def measure_forward(torch, dd, setup, dtype, steps, warmup, stream, numpy_input=None, tune=True):
+def measure_forward(torch, dd, setup, dtype, steps, warmup, stream, numpy_input=None, tune=True, tune_cache=None):
     plan = dd.Plan.from_setup(setup)
     T = plan.input_samples
     if numpy_input is not None:
@@ -174,7 +174,7 @@ def measure_forward(torch, dd, setup, dtype, steps, warmup, stream, numpy_input=
     out = torch.empty((setup.n_dm, setup.n_samples), dtype=torch.float32, device="cuda")
     code = {"f32": dd.DD_F32, "f16": dd.DD_F16, "u8": dd.DD_U8}[dtype]
     if tune:
-        plan.autotune(dd.DD_FORWARD, code, reps=3)   # Sec. IV-A: tune, then measure
+        plan.autotune(dd.DD_FORWARD, code, reps=3, cache_path=tune_cache)   # Sec. IV-A: tune, then measure
     plan.prepare(dd.DD_FORWARD, code)
     t = timed_protocol(torch, lambda: dd.dedisperse(x, plan, out=out), steps, warmup, stream)
     bpe = {"f32": 4, "f16": 2, "u8": 1}[dtype]
@@ -183,10 +183,10 @@ def measure_forward(torch, dd, setup, dtype, steps, warmup, stream, numpy_input=
                 blocks=plan.get_blocks(dtype=code)), plan
 
 
-def measure_adjoint(torch, dd, setup, steps, warmup, stream):
+def measure_adjoint(torch, dd, setup, steps, warmup, stream, tune_cache=None):
     """Tuned adjoint of one beam: gradient rows [D][S] -> [C][T_in]."""
     plan = dd.Plan.from_setup(setup)
-    plan.autotune(dd.DD_ADJOINT, dd.DD_F32, reps=3)
+    plan.autotune(dd.DD_ADJOINT, dd.DD_F32, reps=3, cache_path=tune_cache)
     plan.prepare(dd.DD_ADJOINT, dd.DD_F32)
     g = torch.Generator(device="cuda")
     g.manual_seed(setup.seed)
@@ -470,6 +470,9 @@ def main():
     ap.add_argument("--adjoint", action="store_true",
                     help="time the adjoint of the workload in the headline slot (for its profile)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file for the headline slot (profiling runs reuse the choice a run "
+                         "without counters made: counter collection slows short launches and skews the tuner)")
     ap.add_argument("--realtime", action="store_true",
                     help="only the streaming measurement (Apertif u8 chunks from pinned host memory), one JSON line")
     ap.add_argument("--tune-study", metavar="JSON",
@@ -508,9 +511,10 @@ def main():
     log("workload %s: C=%d D=%d S=%d T_in=%d" % (setup.name, setup.n_channels, setup.n_dm, setup.n_samples,
                                                   plan0.input_samples))
     if args.adjoint:
-        r = measure_adjoint(torch, dd, setup, args.steps, args.warmup, stream)
+        r = measure_adjoint(torch, dd, setup, args.steps, args.warmup, stream, tune_cache=args.tune_cache)
     else:
-        r, plan = measure_forward(torch, dd, setup, "f32", args.steps, args.warmup, stream, numpy_input=x)
+        r, plan = measure_forward(torch, dd, setup, "f32", args.steps, args.warmup, stream, numpy_input=x,
+                                  tune_cache=args.tune_cache)
     ms = r["ms"]
     log("%s f32: %.4f ms/step, %.1f GFLOP/s, %s" % ("adjoint" if args.adjoint else "forward", ms, r["gflops"],
                                                      vdesc(r)))
