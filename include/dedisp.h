@@ -190,10 +190,14 @@ int dd_plan_get_tile(const dd_plan *plan, dd_direction direction, dd_dtype in_ty
  *               rows [row_starts[b], row_starts[b+1]) (the last: to the end);
  *               each start a multiple of its variant's rows per staged chunk
  *   variants    n_blocks tile variants of the LDS or register-window kinds
- * dd_plan_set_blocks forces a split for (direction, in_type) (a later
- * dd_plan_set_tile replaces it); dd_autotune may choose one (Sec. IV-A: the
- * split is timed against the best single variant).  Batches always use one
- * variant per beam.  dd_plan_get_blocks reports the launches the next call
+ * Within a block, each accumulator row's tiles are skewed along time by the
+ * average offset of that row over the block's first and last rows, so that a
+ * tile's rows line up with the delay curve; a shorter block thus needs a
+ * narrower staged window.  dd_plan_set_blocks forces a split for
+ * (direction, in_type) (a later dd_plan_set_tile replaces it); dd_autotune may
+ * choose one (Sec. IV-A: 2-, 3- and 4-block splits, and 8 and 16 blocks where
+ * only the direct kind serves the whole plan, each timed against the best
+ * single variant).  Batches always use one variant per beam.  dd_plan_get_blocks reports the launches the next call
  * makes (one block when there is no split); arrays hold up to DD_MAX_BLOCKS.
  *   DD_EINVAL  bad counts, starts or ids;  DD_EUNSUPPORTED  a variant cannot
  *              serve its block */
