@@ -237,9 +237,13 @@ int dd_batch_create(dd_batch **out, const dd_plan *const *plans, int32_t n_beams
                     dd_dtype in_type);
 
 /* Auto-tune each plan's forward tile (Sec. IV-A) for in_type over every
- * variant, as dd_autotune does; plans of identical shape are timed once per
- * call.  The choice is stored in each plan (so single-beam calls use it too)
- * and read by the next dd_batch_create; cache_path as in dd_autotune.
+ * variant, as dd_autotune does (no row splits); plans of identical shape are
+ * timed once per call.  If one variant serves every beam at most 1% slower
+ * than each beam's own best (times summed over the beams, each timed alone),
+ * every plan gets that variant and the batch becomes a single multi-beam
+ * launch.  The choice is stored in each plan (so single-beam calls use it too)
+ * and read by the next dd_batch_create; cache_path as in dd_autotune (the
+ * common-variant choice is cached under a key of all beams' shapes).
  * Scratch buffers are allocated and freed here.  Synchronises `stream`. */
 int dd_batch_autotune(dd_plan *const *plans, int32_t n_beams, dd_dtype in_type, int32_t reps,
                       const char *cache_path, void *stream);

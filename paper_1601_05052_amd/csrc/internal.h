@@ -197,10 +197,11 @@ int32_t best_by_model(const dd_plan *p, int direction, int32_t in_type, const in
 // here); best id and mean ms.  Synchronises the stream.
 // With split_out, row splits are timed too; *split_out receives the best
 // split if it beats the best single variant (else stays empty) and *best_ms
-// the time of what won.
+// the time of what won.  With times_out, the mean ms of every single variant
+// timed.
 int tune_candidates(const dd_plan *p, int direction, int32_t in_type, int32_t reps, const int32_t *cand,
                     int32_t n_cand, hipStream_t stream, int32_t *best, float *best_ms,
-                    std::vector<Block> *split_out = nullptr);
+                    std::vector<Block> *split_out = nullptr, std::map<int32_t, float> *times_out = nullptr);
 // Free the device tables of row blocks of `direction` that `keep` does not
 // use (the tuner builds one per block and candidate).
 void release_block_tables(const dd_plan *p, int direction, const std::vector<Block> &keep);

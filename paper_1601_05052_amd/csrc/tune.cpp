@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <sstream>
 #include <string>
@@ -154,7 +155,7 @@ static std::vector<std::vector<int32_t>> split_candidates(int32_t R, bool fine) 
 
 int tune_candidates(const dd_plan *p, int direction, int32_t in_type, int32_t reps, const int32_t *cand,
                     int32_t n_cand, hipStream_t stream, int32_t *best_out, float *best_ms_out,
-                    std::vector<Block> *split_out) {
+                    std::vector<Block> *split_out, std::map<int32_t, float> *times_out) {
     const size_t esz = direction == DD_ADJOINT ? 4 : (in_type == DD_F32 ? 4 : in_type == DD_F16 ? 2 : 1);
     const int64_t in_rows = direction == DD_FORWARD ? p->C : p->D;
     const int64_t in_cols = direction == DD_FORWARD ? p->T_in : p->S;
@@ -199,6 +200,8 @@ int tune_candidates(const dd_plan *p, int direction, int32_t in_type, int32_t re
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, e0, e1);
             ms /= reps;
+            if (times_out)
+                (*times_out)[v->id] = ms;
             if (best < 0 || ms < best_t) {
                 best = v->id;
                 best_t = ms;
@@ -288,8 +291,15 @@ namespace {
 // Tune one (plan, direction, dtype): the cache file first, then `memo` (plans
 // of the same shape tuned earlier in this call), else time every variant and,
 // if `splits`, row splits (batches use one variant per beam: no splits).
+struct MemoEntry {
+    int32_t best;
+    float ms;
+    std::map<int32_t, float> times;  // every variant timed (empty when the result came from the cache file)
+};
+
 int tune_one(dd_plan *p, int direction, int32_t in_type, int32_t reps, const char *cache_path, hipStream_t stream,
-             std::map<std::string, std::pair<int32_t, float>> *memo, bool splits, int32_t *best_out, float *ms_out) {
+             std::map<std::string, MemoEntry> *memo, bool splits, int32_t *best_out, float *ms_out,
+             std::map<int32_t, float> *times_out = nullptr) {
     const std::string key = cache_key(p, direction, in_type) + (splits ? "_split" : "");
     int32_t best = -1;
     float best_t = 0.f;
@@ -298,8 +308,10 @@ int tune_one(dd_plan *p, int direction, int32_t in_type, int32_t reps, const cha
     if (memo) {
         auto it = memo->find(key);
         if (it != memo->end()) {
-            best = it->second.first;
-            best_t = it->second.second;
+            best = it->second.best;
+            best_t = it->second.ms;
+            if (times_out)
+                *times_out = it->second.times;
             have = true;
         }
     }
@@ -325,14 +337,14 @@ int tune_one(dd_plan *p, int direction, int32_t in_type, int32_t reps, const cha
         for (int32_t i = 0; i < n; ++i)
             all[i] = i;
         int rc = tune_candidates(p, direction, in_type, reps, all.data(), n, stream, &best, &best_t,
-                                 splits ? &split : nullptr);
+                                 splits ? &split : nullptr, times_out);
         if (rc != DD_OK)
             return rc;
         if (cache_path)
             cache_store(cache_path, key, best, best_t, split);
     }
     if (memo)
-        (*memo)[key] = std::make_pair(best, best_t);
+        (*memo)[key] = MemoEntry{best, best_t, times_out ? *times_out : std::map<int32_t, float>()};
     {
         std::lock_guard<std::mutex> lock(p->mu);
         p->tuned[direction][in_type] = best;
@@ -382,14 +394,82 @@ extern "C" int dd_batch_autotune(dd_plan *const *plans, int32_t n_beams, dd_dtyp
         if (rc != DD_OK)
             return rc;
     }
-    std::map<std::string, std::pair<int32_t, float>> memo;
+    hipStream_t stream = static_cast<hipStream_t>(stream_v);
+    std::map<std::string, MemoEntry> memo;
+    std::vector<std::map<int32_t, float>> times(n_beams);
+    bool complete = true;  // every beam's variants were timed in this call
+    std::string beams_key;
     for (int32_t b = 0; b < n_beams; ++b) {
         int32_t best = -1;
         float best_t = 0.f;
-        int rc = tune_one(plans[b], DD_FORWARD, in_type, reps, cache_path, static_cast<hipStream_t>(stream_v), &memo, false,
-                          &best, &best_t);
+        int rc = tune_one(plans[b], DD_FORWARD, in_type, reps, cache_path, stream, &memo, false, &best, &best_t,
+                          &times[b]);
         if (rc != DD_OK)
             return rc;
+        complete = complete && !times[b].empty();
+        beams_key += cache_key(plans[b], DD_FORWARD, in_type) + ";";
+    }
+    // One variant for every beam, when it costs at most 1% more than each
+    // beam's own best (summed over the beams, each timed alone): the batch is
+    // then a single multi-beam launch.  The choice is cached under a key of
+    // all beams' shapes.
+    char hash[32];
+    std::snprintf(hash, sizeof(hash), "%016llx",
+                  static_cast<unsigned long long>(std::hash<std::string>()(beams_key)));
+    const std::string bkey = std::string("batch|") + hash + "|n" + std::to_string(n_beams) + "|dt" +
+                             std::to_string(static_cast<int>(in_type)) + "|v1";
+    int32_t common = -1;
+    float common_ms = 0.f;
+    std::vector<std::pair<int32_t, int32_t>> unused;
+    bool cached = cache_path && cache_lookup(cache_path, bkey, &common, &common_ms, &unused);
+    if (!cached && complete) {
+        double own = 0.0;
+        for (const auto &t : times) {
+            float m = 0.f;
+            bool first = true;
+            for (const auto &kv : t)
+                if (first || kv.second < m) {
+                    m = kv.second;
+                    first = false;
+                }
+            own += m;
+        }
+        double best_sum = 0.0;
+        for (const auto &kv : times[0]) {
+            double sum = 0.0;
+            bool all = true;
+            for (const auto &t : times) {
+                auto it = t.find(kv.first);
+                if (it == t.end()) {
+                    all = false;
+                    break;
+                }
+                sum += it->second;
+            }
+            if (all && (common < 0 || sum < best_sum)) {
+                common = kv.first;
+                best_sum = sum;
+            }
+        }
+        if (common >= 0 && best_sum > 1.01 * own)
+            common = -1;
+        if (common >= 0) {
+            common_ms = static_cast<float>(best_sum);
+            if (cache_path)
+                cache_store(cache_path, bkey, common, common_ms, {});
+        }
+    }
+    if (common >= 0) {
+        for (int32_t b = 0; b < n_beams; ++b)
+            if (!variant_fits(plans[b], DD_FORWARD, *find_variant(common)))
+                common = -1;
+    }
+    if (common >= 0) {
+        for (int32_t b = 0; b < n_beams; ++b) {
+            std::lock_guard<std::mutex> lock(plans[b]->mu);
+            plans[b]->tuned[DD_FORWARD][in_type] = common;
+            plans[b]->blocks[DD_FORWARD][in_type].clear();
+        }
     }
     return DD_OK;
 }
