@@ -317,3 +317,24 @@ def test_row_split_arguments_checked_on_the_host():
         with pytest.raises(DedispError) as e:   # the adjoint works on float32 rows only
             call()
         assert e.value.code == _lib.DD_EINVAL
+
+
+def test_skewed_tiles_fit_narrower_windows_per_block():
+    """Skewed tiles: within a block of input rows each accumulator row's tiles
+    follow the average delay curve of the block, so the window a tile needs
+    shrinks with the block.  The Apertif adjoint's fan-out across 8 channels
+    reaches 61 samples at the top DM: the 40-register window of variant 31
+    cannot serve all DMs at once, but serves each half; the LOFAR adjoint fits
+    the prefetched LDS tile of variant 46 in 16 blocks of 128 DMs, not in 8."""
+    from paper_1601_05052_amd import DD_ADJOINT
+    p = Plan.from_setup(synth.APERTIF)
+    with pytest.raises(DedispError) as e:
+        p.set_tile(31, direction=DD_ADJOINT)
+    assert e.value.code == _lib.DD_EUNSUPPORTED
+    p.set_blocks([0, 1024], [31, 31], direction=DD_ADJOINT)
+    assert p.get_blocks(direction=DD_ADJOINT) == [(0, 31), (1024, 31)]
+    q = Plan.from_setup(synth.LOFAR)
+    q.set_blocks([128 * k for k in range(16)], [46] * 16, direction=DD_ADJOINT)
+    with pytest.raises(DedispError) as e:
+        q.set_blocks([256 * k for k in range(8)], [46] * 8, direction=DD_ADJOINT)
+    assert e.value.code == _lib.DD_EUNSUPPORTED
