@@ -83,10 +83,33 @@ static void plan_and_layouts(const Setup &s, bool full_tables) {
             const int rc = dd_plan_set_tile(p, static_cast<dd_direction>(dir), DD_F32, v);
             CHECK(rc == DD_OK || rc == DD_EUNSUPPORTED);
             if (full_tables && rc == DD_OK) {
+                const dd::Variant &var = *dd::find_variant(v);
                 dd::Layout L;
-                dd::compute_layout(p, dir, *dd::find_variant(v), true, &L);
+                dd::compute_layout(p, dir, var, true, &L);
                 CHECK(L.feasible);
                 CHECK(L.base.size() == static_cast<size_t>(L.n_tiles) * (dir == 0 ? s.C : s.D));
+                // Skewed tiles: one non-negative multiple of 4 per accumulator
+                // row (or none), and enough time tiles for the largest skew.
+                const int32_t A = dir == 0 ? s.D : s.C;
+                const int64_t n_t = dir == 0 ? s.S : T;
+                int32_t kmax = 0;
+                CHECK(L.skew.empty() || L.skew.size() == static_cast<size_t>(A));
+                for (int32_t k : L.skew) {
+                    CHECK(k >= 0 && k % 4 == 0);
+                    kmax = k > kmax ? k : kmax;
+                }
+                CHECK(static_cast<int64_t>(L.n_t_tiles) * var.tt() >= n_t + kmax);
+                // The second half of the rows as a block of its own (tables
+                // relative to the block; its own skews).
+                const int32_t R = dir == 0 ? s.C : s.D;
+                const int32_t cr = var.kind == dd::KIND_LDS && var.kmax == 0 ? 1 : var.waves * (var.rpw > 0 ? var.rpw : 1);
+                const int32_t r0 = R / 2 / cr * cr;
+                if (dd::block_capable(var) && r0 > 0) {
+                    dd::Layout B;
+                    dd::compute_layout(p, dir, var, true, &B, r0, R);
+                    if (B.feasible)
+                        CHECK(B.base.size() == static_cast<size_t>(B.n_tiles) * (R - r0));
+                }
             }
         }
         CHECK(dd_plan_set_tile(p, static_cast<dd_direction>(dir), DD_F32, -1) == DD_OK);
