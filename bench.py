@@ -498,8 +498,12 @@ def main():
     if args.tune_study:
         study = tune_study(torch, dd, stream)
         with open(args.tune_study, "w") as f:
+            with open(os.path.join(ROOT, VARIANT_LIST)) as vl:
+                curated = len(re.findall(r"X_\w+\(\s*\d+\s*,", re.sub(r"/\*.*?\*/|//[^\n]*", "", vl.read(),
+                                                                        flags=re.S)))
             json.dump({"library": os.path.basename(os.environ.get("DEDISP_LIBRARY") or "libdedisp.so"),
-                       "variants": [list(v) for v in dd.tile_variants()], "instances": study}, f, indent=1)
+                       "curated": curated, "variants": [list(v) for v in dd.tile_variants()], "instances": study},
+                      f, indent=1)
         return
 
     # Headline input: the seeded workload with its pulses (arrivals from the

@@ -38,7 +38,7 @@
         program (its first pass, variants in id order): the mean dispatch
         duration, and the bytes per launch from TRAFFIC_JSON.
 
-    python3 profsum.py study JSON [--curated N]
+    python3 profsum.py study JSON [--curated N]   (N: curated variants; default from the JSON)
         The auto-tuning study (bench.py --tune-study): per instance the
         optimum, mean and spread over the variants that fit, the optimum's
         signal-to-noise ratio and Chebyshev bound, the best fixed variant, the
@@ -339,6 +339,8 @@ def study(path, curated):
     import json
     with open(path) as f:
         d = json.load(f)
+    if curated is None:  # the product list's length when the study ran (46 before it was recorded)
+        curated = d.get("curated", 46)
     var = {v[0]: v for v in d["variants"]}
     rows = d["instances"]
 
@@ -423,7 +425,7 @@ def main(argv=None):
     va.add_argument("traffic_json")
     st = sub.add_parser("study")
     st.add_argument("json")
-    st.add_argument("--curated", type=int, default=46)
+    st.add_argument("--curated", type=int, default=None)
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         trace(a.dir, a.kernel, a.calls_after)
