@@ -243,7 +243,8 @@ int dd_batch_create(dd_batch **out, const dd_plan *const *plans, int32_t n_beams
  * every plan gets that variant and the batch becomes a single multi-beam
  * launch.  The choice is stored in each plan (so single-beam calls use it too)
  * and read by the next dd_batch_create; cache_path as in dd_autotune (the
- * common-variant choice is cached under a key of all beams' shapes).
+ * common-variant choice is cached under a key of all beams' shapes; it is
+ * made only when that key is cached or every beam was timed in this call).
  * Scratch buffers are allocated and freed here.  Synchronises `stream`. */
 int dd_batch_autotune(dd_plan *const *plans, int32_t n_beams, dd_dtype in_type, int32_t reps,
                       const char *cache_path, void *stream);
