@@ -352,17 +352,27 @@ def study(path, curated):
           % (d.get("library"), len(var), curated))
     print()
     print("| setup | DMs | variants | optimum | GFLOP/s | mean | std | SNR | Chebyshev | fixed | tuned / fixed "
-          "| best curated | optimum / best curated | real time |")
-    print("|---|---|---|---|---|---|---|---|---|---|---|---|---|---|")
+          "| best curated | optimum / best curated | model | model / optimum | real time |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|---|---|---|---|---|")
+    ratios = []
     for r in rows:
         g = {int(k): v for k, v in r["gflops"].items()}
         cur = {k: v for k, v in g.items() if k < curated}
         bc = max(cur, key=cur.get) if cur else None
-        print("| %s | %d | %d | %d | %.0f | %.0f | %.0f | %.2f | %.2f | %d | %.2f | %s | %s | %s |" % (
+        mg = r.get("model_gflops")
+        if mg:
+            ratios.append(mg / r["best_gflops"])
+        print("| %s | %d | %d | %d | %.0f | %.0f | %.0f | %.2f | %.2f | %d | %.2f | %s | %s | %s | %s | %s |" % (
             r["setup"], r["n_dm"], r["n_variants"], r["best"], r["best_gflops"], r["mean_gflops"], r["std_gflops"],
             r["snr"], r["chebyshev_bound"], r["fixed_variant"], r["tuned_over_fixed"],
             "-" if bc is None else "%d" % bc, "-" if bc is None else "%.2f" % (r["best_gflops"] / cur[bc]),
+            r.get("model_variant", "-"), "%.2f" % (mg / r["best_gflops"]) if mg else "-",
             "yes" if r["realtime"] else "no"))
+    if ratios:
+        print()
+        print("Untuned cost model (the library's choice without tuning), rated by the measured rate of the "
+              "variant it picks: %.2f-%.2f of the optimum, %.2f on average." % (min(ratios), max(ratios),
+                                                                               sum(ratios) / len(ratios)))
     print()
     print("Optima and fixed variants:")
     print()
