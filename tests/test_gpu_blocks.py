@@ -148,3 +148,21 @@ def test_lofar_adjoint_in_dm_blocks_bit_identical_to_direct():
     for ch in (0, 16, 31):
         ref = oracle.adjoint(gi, np.ascontiguousarray(table[:, ch:ch + 1]), plan.input_samples)[0]
         gates.exact(gx[ch], ref, what="LOFAR adjoint in DM blocks ch %d" % ch)
+
+
+@pytest.mark.parametrize("dtype", [DD_F32, DD_U8])
+def test_split_bit_identical_to_one_variant_apertif_forward(dtype):
+    """Full-size Apertif forward: channels [0, 512) on variant 17 and [512,
+    1024) on variant 31 (each block with its own skews) against variant 31
+    for all channels, bit for bit (N(0,1) float32, or u8)."""
+    s = synth.APERTIF
+    plan = Plan.from_setup(s)
+    if dtype == DD_F32:
+        x = to_dev(synth.noise_f32(s.n_channels, plan.input_samples, seed=96))
+    else:
+        x = to_dev(synth.noise_u8(s.n_channels, plan.input_samples, seed=96))
+    plan.set_tile(31, dtype=dtype)
+    one = to_host(dedisperse(x, plan))
+    plan.set_blocks([0, 512], [17, 31], dtype=dtype)
+    split = to_host(dedisperse(x, plan))
+    assert np.array_equal(one.view(np.uint32), split.view(np.uint32))
