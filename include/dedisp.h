@@ -195,13 +195,13 @@ int dd_plan_get_tile(const dd_plan *plan, dd_direction direction, dd_dtype in_ty
  * tile's rows line up with the delay curve; a shorter block thus needs a
  * narrower staged window.  dd_plan_set_blocks forces a split for
  * (direction, in_type) (a later dd_plan_set_tile replaces it); dd_autotune may
- * choose one (Sec. IV-A: 2-, 3- and 4-block splits, and 8 and 16 blocks where
+ * choose one (Sec. IV-A: 2-, 3- and 4-block splits, and 8, 16 and 32 blocks where
  * only the direct kind serves the whole plan, each timed against the best
  * single variant).  Batches always use one variant per beam.  dd_plan_get_blocks reports the launches the next call
  * makes (one block when there is no split); arrays hold up to DD_MAX_BLOCKS.
  *   DD_EINVAL  bad counts, starts or ids;  DD_EUNSUPPORTED  a variant cannot
  *              serve its block */
-#define DD_MAX_BLOCKS 16
+#define DD_MAX_BLOCKS 32
 int dd_plan_set_blocks(dd_plan *plan, dd_direction direction, dd_dtype in_type, int32_t n_blocks,
                        const int32_t *row_starts, const int32_t *variants);
 int dd_plan_get_blocks(const dd_plan *plan, dd_direction direction, dd_dtype in_type, int32_t *n_blocks,

@@ -8,7 +8,7 @@ from .build import library_path
 
 DD_OK, DD_EINVAL, DD_ESHAPE, DD_ENOMEM, DD_EHIP, DD_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 DD_F32, DD_F16, DD_U8 = 0, 1, 2
-DD_MAX_BLOCKS = 16
+DD_MAX_BLOCKS = 32
 DD_FORWARD, DD_ADJOINT = 0, 1
 
 STATUS_NAMES = {0: "DD_OK", -1: "DD_EINVAL", -2: "DD_ESHAPE", -3: "DD_ENOMEM", -4: "DD_EHIP",

@@ -131,14 +131,14 @@ static int time_blocks(const dd_plan *p, int direction, int32_t in_t, const std:
 // Row splits tried by the tuner: the rows cut into 2, 3 or 4 blocks of about
 // equal size at multiples of 64 rows (a multiple of every variant's rows per
 // chunk), at least 64 rows each; every block is timed alone with every
-// variant that can serve it.  With `fine` also 8 and 16 blocks: where only
+// variant that can serve it.  With `fine` also 8, 16 and 32 blocks: where only
 // the direct kind serves all rows at once (no staged window fits), short
 // blocks can bring the skewed tiles' window within a staged kind's reach.
 static std::vector<std::vector<int32_t>> split_candidates(int32_t R, bool fine) {
     std::vector<std::vector<int32_t>> out;
     if (R < 256)
         return out;
-    for (int32_t nb : {2, 3, 4, 8, 16}) {
+    for (int32_t nb : {2, 3, 4, 8, 16, 32}) {
         if (R / nb < 64 || (nb > 4 && !fine))
             break;
         std::vector<int32_t> starts{0};

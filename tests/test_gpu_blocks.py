@@ -127,21 +127,20 @@ def test_noalloc_with_split():
 
 
 def test_lofar_adjoint_in_dm_blocks_bit_identical_to_direct():
-    """Full-size LOFAR adjoint on N(0,1) data: sixteen blocks of 128 DMs, each
-    on a prefetched LDS tile of 8 channels (skewed tiles, row spans), against
-    the direct kind over all DMs at once: the same rows in the same order, so
-    bit-identical; and exact against the oracle on integer data for three
-    channels."""
+    """Full-size LOFAR adjoint on N(0,1) data: sixteen blocks of 128 DMs, or
+    thirty-two of 64, each on a prefetched LDS tile of 8 channels (skewed
+    tiles, row spans), against the direct kind over all DMs at once: the same
+    rows in the same order, so bit-identical; and exact against the oracle on
+    integer data for three channels."""
     s = synth.LOFAR
     plan = Plan.from_setup(s)
-    starts = [128 * k for k in range(16)]
     gy = to_dev(synth.noise_f32(s.n_dm, s.n_samples, seed=94))
     plan.set_tile(45, direction=DD_ADJOINT)
     one = run(plan, gy, DD_ADJOINT)
-    for v in (46, 25):
-        plan.set_blocks(starts, [v] * 16, direction=DD_ADJOINT)
+    for nb, v in ((16, 46), (16, 25), (32, 37)):
+        plan.set_blocks([(s.n_dm // nb) * k for k in range(nb)], [v] * nb, direction=DD_ADJOINT)
         split = run(plan, gy, DD_ADJOINT)
-        assert np.array_equal(one.view(np.uint32), split.view(np.uint32)), v
+        assert np.array_equal(one.view(np.uint32), split.view(np.uint32)), (nb, v)
     table = oracle_delays(s)
     gi = synth.integers_f32(s.n_dm, s.n_samples, seed=95, lo=-3, hi=3)
     gx = run(plan, to_dev(gi), DD_ADJOINT)

@@ -310,6 +310,14 @@ def test_row_split_arguments_checked_on_the_host():
     assert p.get_blocks() == [(0, 0)]
     p.set_blocks([0, 64], [9, 9], direction=DD_ADJOINT)   # adjoint rows are the 128 DMs
     assert p.get_blocks(direction=DD_ADJOINT) == [(0, 9), (64, 9)]
+    n = _lib.DD_MAX_BLOCKS
+    with open(os.path.join(ROOT, "include", "dedisp.h")) as f:
+        assert "#define DD_MAX_BLOCKS %d\n" % n in f.read()
+    p.set_blocks([4 * k for k in range(n)], [9] * n, direction=DD_ADJOINT)
+    assert p.get_blocks(direction=DD_ADJOINT) == [(4 * k, 9) for k in range(n)]
+    with pytest.raises(DedispError) as e:      # one block more than the arrays hold
+        p.set_blocks([2 * k for k in range(n + 1)], [9] * (n + 1), direction=DD_ADJOINT)
+    assert e.value.code == _lib.DD_EINVAL
     assert p.get_blocks(direction=DD_FORWARD) == [(0, 0)]
     from paper_1601_05052_amd import DD_U8
     for call in (lambda: p.set_blocks([0, 64], [9, 9], direction=DD_ADJOINT, dtype=DD_U8),
