@@ -98,6 +98,18 @@ def test_plan_rejects_invalid(bad):
     assert _lib.lib().dd_last_error()
 
 
+def test_plan_size_limit():
+    """Input rows (n_samples + max delay) must stay below 2^29 samples: the
+    largest such plan is accepted, one sample more is refused."""
+    args = (4, 1400.0, 1.0, 5e-5, 0.0, 80.0, 4)
+    md = int(oracle.delay_table(*args).max())
+    assert md > 0
+    assert Plan(*args, (1 << 29) - 1 - md).input_samples == (1 << 29) - 1
+    with pytest.raises(DedispError) as e:
+        Plan(*args, (1 << 29) - md)
+    assert e.value.code == _lib.DD_EINVAL
+
+
 def _fake(addr):
     return ctypes.c_void_p(addr)
 
