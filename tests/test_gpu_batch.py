@@ -75,6 +75,30 @@ def test_batch_mixed_forced_variants_exact():
         gates.exact(to_host(y), oracle.dedisperse(x, table, b.n_samples), what=b.name)
 
 
+def test_batch_of_the_most_beams_exact():
+    """The largest batch (96 beams) of uneven small beams, degenerate ones
+    included (one channel, one DM, one sample), u8 storage: one graph launch,
+    every beam bit-exact against the oracle and against its single-beam run."""
+    rng = np.random.default_rng(96)
+    beams = [synth.Setup("one", 1, 1400.0, 1.0, 5e-5, 0.0, 1.0, 1, 1, seed=1000)]
+    for b in range(1, 96):
+        c = int(rng.choice([1, 3, 16, 64, 130]))
+        d = int(rng.choice([1, 7, 40, 129]))
+        s = int(rng.choice([1, 65, 513, 2000]))
+        beams.append(synth.Setup("mb%d" % b, c, 1420.0, 300.0 / c, 1.0 / 20000, 0.0, 0.25 * (1 + b % 5), d, s,
+                                 seed=1000 + b))
+    plans = [Plan.from_setup(b) for b in beams]
+    xs_h = [synth.noise_u8(b.n_channels, p.input_samples, b.seed) for b, p in zip(beams, plans)]
+    batch = Batch(plans, dtype=DD_U8)
+    assert len(batch.variants()) == 96
+    outs = batch.run([to_dev(x) for x in xs_h])
+    for b, p, x, y in zip(beams, plans, xs_h, outs):
+        yh = to_host(y)
+        table = oracle.delay_table(*b.plan_args()[:7])
+        gates.exact(yh, oracle.dedisperse(x, table, b.n_samples), what=b.name)
+        assert np.array_equal(to_host(dedisperse(to_dev(x), p)), yh), b.name
+
+
 def test_batch_replay_new_data_and_pointers():
     torch = torch_mod()
     beams = small_beams()[:4]

@@ -151,6 +151,12 @@ def test_null_plan_queries():
     assert L.dd_plan_destroy(None) == _lib.DD_OK
     assert L.dd_batch_destroy(None) == _lib.DD_OK
     assert L.dd_batch_create(None, None, 0, 0) == _lib.DD_EINVAL
+    tiny = Plan.from_setup(synth.TINY)
+    many = (ctypes.c_void_p * 97)(*([tiny.handle.value] * 97))
+    b = ctypes.c_void_p()
+    assert L.dd_batch_create(ctypes.byref(b), many, 97, 0) == _lib.DD_EINVAL   # at most 96 beams
+    assert L.dd_batch_create(ctypes.byref(b), many, 0, 0) == _lib.DD_EINVAL
+    assert not b.value
     assert L.dd_batch_autotune(None, 0, 0, 1, None, None) == _lib.DD_EINVAL
     p = Plan.from_setup(synth.TINY)
     arr = (ctypes.c_void_p * 1)(p.handle.value)
