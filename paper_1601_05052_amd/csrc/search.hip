@@ -47,6 +47,8 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
     return s;
 }
 
+typedef float v4f __attribute__((ext_vector_type(4)));
+
 struct Cand {
     float snr;
     int32_t t;
@@ -67,7 +69,7 @@ __global__ __launch_bounds__(kSearchThreads) void boxcar_search_kernel(const flo
                                                                      float *__restrict__ snr_out,
                                                                      int32_t *__restrict__ t_out,
                                                                      int32_t *__restrict__ w_out) {
-    __shared__ float box[kExt];
+    __shared__ __attribute__((aligned(16))) float box[kExt];
     __shared__ double red[kSearchThreads / 64];
     __shared__ Cand cred[kSearchThreads];
     const int tid = threadIdx.x;
@@ -141,37 +143,77 @@ __global__ __launch_bounds__(kSearchThreads) void boxcar_search_kernel(const flo
             // same pass, forms B_2w(i) = B_w(i) + B_w(i + w) for i + 2w <= kExt:
             // all reads, then a barrier, then the writes, so no thread reads a
             // value already doubled.
-            constexpr int kPer = (kExt + kSearchThreads - 1) / kSearchThreads;
-            static_assert(kChunk % kSearchThreads == 0, "chunk starts split evenly over the threads");
+            // Thread tid holds the quads j = tid + q * kSearchThreads (samples
+            // 4j .. 4j + 3): 16-byte LDS reads and writes throughout.
+            constexpr int kQ = kExt / (4 * kSearchThreads);       // quads per thread
+            constexpr int kQOwn = kChunk / (4 * kSearchThreads);  // of which hold starts of this chunk
+            constexpr int kOwn = 4 * kQOwn;                       // starts this thread scores per chunk
+            static_assert(kExt % (4 * kSearchThreads) == 0 && kChunk % (4 * kSearchThreads) == 0,
+                          "chunk and halo split evenly into quads over the threads");
+            static_assert((kOwn & (kOwn - 1)) == 0, "pairwise argmax over a power of two");
+            v4f *box4 = reinterpret_cast<v4f *>(box);
             for (int32_t w = 1;; w *= 2) {
                 // 1/sqrt(w) correctly rounded (exact for even powers of two),
                 // so boxcars whose binary64 S/N tie also tie here.
                 const float scale = inv_sigma * static_cast<float>(1.0 / sqrt(static_cast<double>(w)));
                 const bool last = w >= wmax;
-                float nv[kPer];
+                // starts c0 + i with i <= lim end inside the row (i < kExt here)
+                const int32_t lim = static_cast<int32_t>(min(S - c0 - w, static_cast<int64_t>(kExt)));
+                v4f nv[kQ];
+                float sv[kOwn];
+                int32_t sk[kOwn];
 #pragma unroll
-                for (int k = 0; k < kPer; ++k) {
-                    const int i = tid + k * kSearchThreads;
-                    const float b = i < kExt ? box[i] : 0.f;
-                    if (k < kChunk / kSearchThreads) {
-                        const int64_t t = c0 + i;
-                        if (t + w <= S) {
-                            const Cand c{b * scale, static_cast<int32_t>(t), w};
-                            if (better(c, best))
-                                best = c;
+                for (int q = 0; q < kQ; ++q) {
+                    const int j = tid + q * kSearchThreads;
+                    const v4f b = box4[j];
+                    if (q < kQOwn) {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            // starts past S - w score -inf, which no valid start loses to
+                            sv[4 * q + e] = 4 * j + e <= lim ? b[e] * scale : -INFINITY;
+                            sk[4 * q + e] = 4 * q + e;
                         }
                     }
-                    nv[k] = !last && i + 2 * w <= kExt ? b + box[i + w] : 0.f;
+                    if (!last) {
+                        // B_w at samples 4j + e + w: a whole quad w/4 quads on for
+                        // w >= 4, else the tail of this quad and the head of the next.
+                        v4f u;
+                        if (w >= 4) {
+                            const int jw = j + (w >> 2);
+                            u = jw < kExt / 4 ? box4[jw] : v4f{0.f, 0.f, 0.f, 0.f};
+                        } else {
+                            const v4f n = j + 1 < kExt / 4 ? box4[j + 1] : v4f{0.f, 0.f, 0.f, 0.f};
+                            u = w == 1 ? v4f{b.y, b.z, b.w, n.x} : v4f{b.z, b.w, n.x, n.y};
+                        }
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            nv[q][e] = 4 * j + e + 2 * w <= kExt ? b[e] + u[e] : 0.f;
+                    }
+                }
+                // This width's best start among this thread's (index 4q + e
+                // grows with the start), pairwise over neighbouring runs: the
+                // earlier run's pick is kept unless the later one scores
+                // higher (a NaN never wins, as in better()).
+#pragma unroll
+                for (int h = 1; h < kOwn; h *= 2)
+#pragma unroll
+                    for (int k = 0; k < kOwn; k += 2 * h)
+                        if (sv[k + h] == sv[k + h] && !(sv[k + h] <= sv[k])) {
+                            sv[k] = sv[k + h];
+                            sk[k] = sk[k + h];
+                        }
+                if (sv[0] > -INFINITY) {
+                    const int32_t k = sk[0];
+                    const Cand c{sv[0], static_cast<int32_t>(c0 + 4 * (tid + (k >> 2) * kSearchThreads) + (k & 3)), w};
+                    if (better(c, best))
+                        best = c;
                 }
                 if (last)
                     break;
                 __syncthreads();
 #pragma unroll
-                for (int k = 0; k < kPer; ++k) {
-                    const int i = tid + k * kSearchThreads;
-                    if (i < kExt)
-                        box[i] = nv[k];
-                }
+                for (int q = 0; q < kQ; ++q)
+                    box4[tid + q * kSearchThreads] = nv[q];
                 __syncthreads();
             }
         }
