@@ -47,8 +47,12 @@ KERNEL_SOURCES = ["paper_1601_05052_amd/csrc/" + n for n in (
 VARIANT_LIST = "paper_1601_05052_amd/csrc/srs_variants.def"
 
 
+_T0 = time.monotonic()
+
+
 def log(msg):
-    print(msg, file=sys.stderr, flush=True)
+    """Progress line on stderr, prefixed by the seconds since start."""
+    print("[%6.1fs] %s" % (time.monotonic() - _T0, msg), file=sys.stderr, flush=True)
 
 
 def kernel_source_hash():

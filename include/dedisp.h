@@ -210,7 +210,9 @@ int dd_plan_get_blocks(const dd_plan *plan, dd_direction direction, dd_dtype in_
 /* Auto-tuning, Sec. IV-A: time every tile variant that can serve this plan
  * on the current device (mean of `reps` runs after one warm-up, on private
  * scratch buffers allocated and freed here), keep the fastest for
- * (direction, in_type) and report it.  If cache_path is non-NULL, the result
+ * (direction, in_type) and report it.  Variants are timed in the cost model's
+ * order; one whose warm-up run takes over 3x the best mean so far is not run
+ * again (its warm-up time stands).  If cache_path is non-NULL, the result
  * is looked up in / appended to that text file, keyed by device architecture,
  * direction, dtype and plan shape.  Synchronises `stream`.
  *   best_variant  out, may be NULL

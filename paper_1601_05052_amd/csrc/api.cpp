@@ -37,20 +37,6 @@ int resolve_variant(const dd_plan *p, int direction, int32_t in_type, const Vari
 namespace dd {
 
 // Shared by the public calls and the tuner: checks done by the caller.
-int run_direction(const dd_plan *p, int direction, int32_t in_type, const Variant &v, const void *in,
-                  int64_t in_stride, float *out, int64_t out_stride, hipStream_t stream) {
-    if (!has_kernel(v, direction == DD_FORWARD ? in_type : (int32_t)DD_F32))
-        return fail(DD_EUNSUPPORTED, "this library has no kernel of tile variant %d for this input type", v.id);
-    SrsArgs a;
-    int rc = make_args(p, direction, v, in, in_stride, out, out_stride, &a);
-    if (rc != DD_OK)
-        return rc;
-    hipError_t e = launch_srs(v, direction == DD_FORWARD ? in_type : (int32_t)DD_F32, a, stream);
-    if (e != hipSuccess)
-        return fail(DD_EHIP, "kernel launch failed: %s", hipGetErrorString(e));
-    return DD_OK;
-}
-
 int run_blocks(const dd_plan *p, int direction, int32_t in_type, const std::vector<Block> &blocks, const void *in,
                int64_t in_stride, float *out, int64_t out_stride, hipStream_t stream) {
     const int32_t kt = direction == DD_FORWARD ? in_type : (int32_t)DD_F32;

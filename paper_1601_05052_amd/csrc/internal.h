@@ -193,6 +193,9 @@ int32_t choose_variant(const dd_plan *p, int direction, int32_t in_type);
 int32_t resolved_variant(const dd_plan *p, int direction, int32_t in_type);
 // Cost-model choice among `cand` (ids) that fit; -1 if none fits.
 int32_t best_by_model(const dd_plan *p, int direction, int32_t in_type, const int32_t *cand, int32_t n_cand);
+// The cost model's time for a variant over rows [r0, r1) of the plan (r1 < 0:
+// all rows), in seconds, after variant_fits has accepted it for those rows.
+double model_seconds(const dd_plan *p, int direction, const Variant &v, int32_t r0 = 0, int32_t r1 = -1);
 // Time the candidates on the plan's own sizes (scratch buffers allocated
 // here); best id and mean ms.  Synchronises the stream.
 // With split_out, row splits are timed too; *split_out receives the best

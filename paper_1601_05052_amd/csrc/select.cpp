@@ -17,8 +17,7 @@ namespace dd {
 // staged input samples at an L2-to-LDS rate (the direct kind stages none).  Rates and both constants were
 // fitted to every variant's measured time on Apertif- and LOFAR-shaped beams
 // of 2 to 4,096 trial DMs on MI355X.
-static double estimate_seconds(const dd_plan *p, int direction, const Variant &v, int32_t wcap) {
-    const int32_t R = direction == DD_FORWARD ? p->C : p->D;
+static double estimate_seconds(const dd_plan *p, int direction, const Variant &v, int32_t wcap, int32_t R) {
     const int32_t A = direction == DD_FORWARD ? p->D : p->C;
     const int64_t n_t = direction == DD_FORWARD ? p->S : p->T_in;
     const double n_t_tiles = static_cast<double>((n_t + v.tt() - 1) / v.tt());
@@ -31,6 +30,19 @@ static double estimate_seconds(const dd_plan *p, int direction, const Variant &v
     return work / (static_cast<double>(v.rate) * 1e12 * fill) + staged / 8e12;
 }
 
+double model_seconds(const dd_plan *p, int direction, const Variant &v, int32_t r0, int32_t r1) {
+    if (r1 < 0)
+        r1 = plan_rows(p, direction);
+    int32_t wcap = 0;
+    {
+        std::lock_guard<std::mutex> lock(p->mu);
+        auto it = p->fit.find(std::make_tuple(direction, (int)v.id, (int)r0, (int)r1));
+        if (it != p->fit.end())
+            wcap = std::get<1>(it->second);
+    }
+    return estimate_seconds(p, direction, v, wcap, r1 - r0);
+}
+
 int32_t best_by_model(const dd_plan *p, int direction, int32_t in_type, const int32_t *cand, int32_t n_cand) {
     int32_t best = -1;
     double best_t = 0.0;
@@ -39,12 +51,7 @@ int32_t best_by_model(const dd_plan *p, int direction, int32_t in_type, const in
         const Variant *v = find_variant(cand[i]);
         if (!v || !has_kernel(*v, kt) || !variant_fits(p, direction, *v))
             continue;
-        int32_t wcap = 0;
-        {
-            std::lock_guard<std::mutex> lock(p->mu);
-            wcap = std::get<1>(p->fit[std::make_tuple(direction, (int)v->id, 0, (int)plan_rows(p, direction))]);
-        }
-        const double t = estimate_seconds(p, direction, *v, wcap);
+        const double t = model_seconds(p, direction, *v);
         if (best < 0 || t < best_t) {
             best = v->id;
             best_t = t;

@@ -18,11 +18,6 @@
 
 #include "internal.h"
 
-namespace dd {
-int run_direction(const dd_plan *p, int direction, int32_t in_type, const Variant &v, const void *in,
-                  int64_t in_stride, float *out, int64_t out_stride, hipStream_t stream);
-}
-
 using namespace dd;
 
 namespace {
@@ -111,22 +106,49 @@ void cache_store(const char *path, const std::string &key, int32_t variant, floa
 namespace dd {
 
 // Mean milliseconds of `reps` runs of one launch list, after one warm-up run.
+// The tables are built first, so the warm-up run times the kernels alone; if
+// it takes longer than cap_ms (> 0), its time is returned without the
+// repeated runs (a variant that slow cannot win, and some are very slow:
+// staged windows far wider than their tiles).
 static int time_blocks(const dd_plan *p, int direction, int32_t in_t, const std::vector<Block> &blocks, int32_t reps,
                        const void *d_in, int64_t in_cols, float *d_out, int64_t out_cols, hipStream_t stream,
-                       hipEvent_t e0, hipEvent_t e1, float *ms) {
+                       hipEvent_t e0, hipEvent_t e1, float *ms, float cap_ms = 0.f) {
+    for (const Block &b : blocks) {
+        const Variant *v = find_variant(b.variant);
+        const TileTables *t = nullptr;
+        const int rc = v ? plan_tables(p, direction, *v, &t, b.r0, b.r1) : fail(DD_EINVAL, "unknown tile variant");
+        if (rc != DD_OK)
+            return rc;
+    }
+    (void)hipEventRecord(e0, stream);
     int rc = run_blocks(p, direction, in_t, blocks, d_in, in_cols, d_out, out_cols, stream);
+    (void)hipEventRecord(e1, stream);
     if (rc != DD_OK)
         return rc;
+    if (hipEventSynchronize(e1) != hipSuccess)
+        return fail(DD_EHIP, "tuning run failed");
+    float warm = 0.f;
+    (void)hipEventElapsedTime(&warm, e0, e1);
+    if (cap_ms > 0.f && warm > cap_ms) {
+        *ms = warm;
+        return DD_OK;
+    }
     (void)hipEventRecord(e0, stream);
     for (int32_t r = 0; r < reps && rc == DD_OK; ++r)
         rc = run_blocks(p, direction, in_t, blocks, d_in, in_cols, d_out, out_cols, stream);
     (void)hipEventRecord(e1, stream);
+    if (rc != DD_OK)
+        return rc;
     if (hipEventSynchronize(e1) != hipSuccess)
         return fail(DD_EHIP, "tuning run failed");
     (void)hipEventElapsedTime(ms, e0, e1);
     *ms /= reps;
     return rc;
 }
+
+// A variant whose first run takes longer than this many times the fastest
+// mean so far is not run again.
+constexpr float kPruneFactor = 3.f;
 
 // Row splits tried by the tuner: the rows cut into 2, 3 or 4 blocks of about
 // equal size at multiples of 64 rows (a multiple of every variant's rows per
@@ -182,28 +204,29 @@ int tune_candidates(const dd_plan *p, int direction, int32_t in_type, int32_t re
             break;
         }
         const int32_t in_t = direction == DD_FORWARD ? in_type : (int32_t)DD_F32;
-        for (int32_t i = 0; i < n_cand && rc == DD_OK; ++i) {
+        const int32_t R = plan_rows(p, direction);
+        // Candidates that fit, in the cost model's order (fastest expected
+        // first), so the slow ones meet a low pruning bound.
+        std::vector<std::pair<double, int32_t>> order;
+        for (int32_t i = 0; i < n_cand; ++i) {
             const Variant *v = find_variant(cand[i]);
-            if (!v || !has_kernel(*v, in_t) || !variant_fits(p, direction, *v))
-                continue;
-            rc = run_direction(p, direction, in_t, *v, d_in, in_cols, d_out, out_cols, stream);  // warm-up
+            if (v && has_kernel(*v, in_t) && variant_fits(p, direction, *v))
+                order.emplace_back(model_seconds(p, direction, *v), v->id);
+        }
+        std::stable_sort(order.begin(), order.end(),
+                         [](const std::pair<double, int32_t> &a, const std::pair<double, int32_t> &b) {
+                             return a.first < b.first;
+                         });
+        for (const auto &o : order) {
+            float ms = 0.f;
+            rc = time_blocks(p, direction, in_t, {Block{0, R, o.second}}, reps, d_in, in_cols, d_out, out_cols, stream,
+                             e0, e1, &ms, best < 0 ? 0.f : kPruneFactor * best_t);
             if (rc != DD_OK)
                 break;
-            (void)hipEventRecord(e0, stream);
-            for (int32_t r = 0; r < reps && rc == DD_OK; ++r)
-                rc = run_direction(p, direction, in_t, *v, d_in, in_cols, d_out, out_cols, stream);
-            (void)hipEventRecord(e1, stream);
-            if (hipEventSynchronize(e1) != hipSuccess) {
-                rc = fail(DD_EHIP, "tuning run failed");
-                break;
-            }
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, e0, e1);
-            ms /= reps;
             if (times_out)
-                (*times_out)[v->id] = ms;
+                (*times_out)[o.second] = ms;
             if (best < 0 || ms < best_t) {
-                best = v->id;
+                best = o.second;
                 best_t = ms;
             }
         }
@@ -211,7 +234,6 @@ int tune_candidates(const dd_plan *p, int direction, int32_t in_type, int32_t re
             break;
         // Row splits: each block's fastest variant, timed alone; the split
         // replaces the single variant only if it is faster by more than 2%.
-        const int32_t R = plan_rows(p, direction);
         float split_t = 0.98f * best_t;
         const bool fine = find_variant(best)->kind == KIND_DIRECT;
         for (const std::vector<int32_t> &starts : split_candidates(R, fine)) {
@@ -221,15 +243,24 @@ int tune_candidates(const dd_plan *p, int direction, int32_t in_type, int32_t re
                 const int32_t r0 = starts[b], r1 = b + 1 < starts.size() ? starts[b + 1] : R;
                 Block bb{r0, r1, -1};
                 float bb_t = 0.f;
-                for (int32_t i = 0; i < n_cand && rc == DD_OK; ++i) {
+                std::vector<std::pair<double, int32_t>> border;  // this block's candidates, model order
+                for (int32_t i = 0; i < n_cand; ++i) {
                     const Variant *v = find_variant(cand[i]);
-                    if (!v || !block_capable(*v) || !has_kernel(*v, in_t) || !variant_fits(p, direction, *v, r0, r1))
-                        continue;
+                    if (v && block_capable(*v) && has_kernel(*v, in_t) && variant_fits(p, direction, *v, r0, r1))
+                        border.emplace_back(model_seconds(p, direction, *v, r0, r1), v->id);
+                }
+                std::stable_sort(border.begin(), border.end(),
+                                 [](const std::pair<double, int32_t> &a, const std::pair<double, int32_t> &b) {
+                                     return a.first < b.first;
+                                 });
+                for (const auto &o : border) {
                     float ms = 0.f;
-                    rc = time_blocks(p, direction, in_t, {Block{r0, r1, v->id}}, reps, d_in, in_cols, d_out, out_cols,
-                                     stream, e0, e1, &ms);
-                    if (rc == DD_OK && (bb.variant < 0 || ms < bb_t)) {
-                        bb.variant = v->id;
+                    rc = time_blocks(p, direction, in_t, {Block{r0, r1, o.second}}, reps, d_in, in_cols, d_out,
+                                     out_cols, stream, e0, e1, &ms, bb.variant < 0 ? 0.f : kPruneFactor * bb_t);
+                    if (rc != DD_OK)
+                        break;
+                    if (bb.variant < 0 || ms < bb_t) {
+                        bb.variant = o.second;
                         bb_t = ms;
                     }
                 }
@@ -237,6 +268,8 @@ int tune_candidates(const dd_plan *p, int direction, int32_t in_type, int32_t re
                     break;
                 blocks.push_back(bb);
                 total += bb_t;
+                if (total >= split_t)
+                    break;  // already slower than the best so far: the other blocks need no timing
             }
             if (rc != DD_OK)
                 break;
