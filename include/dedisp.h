@@ -212,7 +212,8 @@ int dd_plan_get_blocks(const dd_plan *plan, dd_direction direction, dd_dtype in_
  * scratch buffers allocated and freed here), keep the fastest for
  * (direction, in_type) and report it.  Variants are timed in the cost model's
  * order; one whose warm-up run takes over 3x the best mean so far is not run
- * again (its warm-up time stands).  If cache_path is non-NULL, the result
+ * again (its warm-up time stands); the three fastest are timed twice and
+ * ranked by the mean of both.  If cache_path is non-NULL, the result
  * is looked up in / appended to that text file, keyed by device architecture,
  * direction, dtype and plan shape.  Synchronises `stream`.
  *   best_variant  out, may be NULL
