@@ -149,6 +149,9 @@ static int time_blocks(const dd_plan *p, int direction, int32_t in_t, const std:
 // A variant whose first run takes longer than this many times the fastest
 // mean so far is not run again.
 constexpr float kPruneFactor = 3.f;
+// A split is timed as a whole when its blocks, each timed alone, add up to
+// less than this many times the time to beat.
+constexpr float kSplitSlack = 1.05f;
 
 // Row splits tried by the tuner: the rows cut into 2, 3 or 4 blocks of about
 // equal size at multiples of 64 rows (a multiple of every variant's rows per
@@ -301,13 +304,16 @@ int tune_candidates(const dd_plan *p, int direction, int32_t in_type, int32_t re
                     break;
                 blocks.push_back(bb);
                 total += bb_t;
-                if (total >= split_t)
+                if (total >= kSplitSlack * split_t)
                     break;  // already slower than the best so far: the other blocks need no timing
             }
             if (rc != DD_OK)
                 break;
-            if (blocks.size() == starts.size() && total < split_t) {
-                // Confirm the split as one call (the blocks back to back).
+            if (blocks.size() == starts.size() && total < kSplitSlack * split_t) {
+                // Confirm the split as one call (the blocks back to back; a
+                // block timed alone can take a few per cent longer than
+                // after the previous one, whose partial sums are still in
+                // the caches).
                 float ms = 0.f;
                 rc = time_blocks(p, direction, in_t, blocks, reps, d_in, in_cols, d_out, out_cols, stream, e0, e1, &ms);
                 if (rc == DD_OK && ms < split_t) {
