@@ -87,6 +87,9 @@ static void plan_and_layouts(const Setup &s, bool full_tables) {
                 dd::Layout L;
                 dd::compute_layout(p, dir, var, true, &L);
                 CHECK(L.feasible);
+                // the cost model the tuner orders its candidates by
+                const double est = dd::model_seconds(p, dir, var);
+                CHECK(est > 0.0 && est < 1e6);
                 CHECK(L.base.size() == static_cast<size_t>(L.n_tiles) * (dir == 0 ? s.C : s.D));
                 // Skewed tiles: one non-negative multiple of 4 per accumulator
                 // row (or none), and enough time tiles for the largest skew.
@@ -107,8 +110,12 @@ static void plan_and_layouts(const Setup &s, bool full_tables) {
                 if (dd::block_capable(var) && r0 > 0) {
                     dd::Layout B;
                     dd::compute_layout(p, dir, var, true, &B, r0, R);
-                    if (B.feasible)
+                    if (B.feasible) {
                         CHECK(B.base.size() == static_cast<size_t>(B.n_tiles) * (R - r0));
+                        CHECK(dd::variant_fits(p, dir, var, r0, R));
+                        const double eb = dd::model_seconds(p, dir, var, r0, R);
+                        CHECK(eb > 0.0 && eb < 1e6);
+                    }
                 }
             }
         }
